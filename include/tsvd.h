@@ -1,0 +1,179 @@
+/*
+ * tsvd.h -- C ABI of the MI355X (gfx950) truncated-SVD library.
+ *
+ * The library computes the k leading singular triplets of a real matrix A by
+ * the power method with deflation (Boureima et al., "Distributed
+ * Out-of-Memory SVD on CPU/GPU Architectures": Algorithm 1, the driver;
+ * Algorithm 2, the power method on the Gram matrix; Algorithm 3, the Gram as
+ * a sum of block products; Equations 1-3 and Algorithm 4, the deflated
+ * product applied to a vector without forming the residual).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All matrices are dense and addressed by plain pointers and leading
+ *   dimensions.  A is ROW-major (element (i, j) at A[i * lda + j], lda >= n).
+ *   U (m x k), V (n x k) and the iterate matrices X are COLUMN-major (column j
+ *   contiguous at X + j * ldx, ldx >= rows): one singular vector per column.
+ *   Gram matrices B are stored in full (both triangles), row-major, ldb >= d.
+ * - Device pointers are HIP device allocations on the context's device
+ *   (torch.cuda tensors qualify).  "host" pointers are ordinary host memory
+ *   unless stated "pinned".
+ * - The caller owns A, the CSR arrays and every output buffer.  The library
+ *   only borrows them for the duration of the call.  The library owns the
+ *   context, its workspaces and its internal streams.
+ * - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Entry
+ *   points that return a status derived from device results (convergence,
+ *   rank deficiency) synchronise `stream` before returning; those documented
+ *   as "asynchronous" do not.
+ * - Nothing throws across the ABI.  On failure the status says what went
+ *   wrong and tsvd_last_error(ctx) holds a message (per context).
+ * - Calls on one context are not thread safe; use one context per host thread.
+ *
+ * Sign convention: the largest-magnitude entry of each v_j is positive (ties:
+ * lowest index) and u_j follows from u_j = A v_j / sigma_j.
+ */
+#ifndef TSVD_H
+#define TSVD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TSVD_OK = 0,
+  TSVD_ERR_INVALID_ARG = 1,    /* bad shape, k, pointer, leading dimension or option */
+  TSVD_ERR_OUT_OF_MEMORY = 2,  /* device allocation failed or would exceed opts.hbm_budget */
+  TSVD_ERR_NOT_CONVERGED = 3,  /* eps > 0 and some triplet hit max_iter; all outputs are still filled */
+  TSVD_ERR_NONFINITE = 4,      /* NaN/Inf met in the Gram, a product or a norm */
+  TSVD_ERR_HIP = 5,            /* a HIP runtime call failed */
+  TSVD_ERR_REJECTED = 6,       /* the server cannot admit the request even when idle */
+  TSVD_ERR_UNSUPPORTED = 7,    /* valid request outside what this build implements */
+  TSVD_ERR_INTERNAL = 8        /* an internal consistency check failed (e.g. a bounded device wait timed out) */
+} tsvd_status;
+
+typedef enum { TSVD_F32 = 0, TSVD_F64 = 1 } tsvd_dtype;
+
+typedef enum { TSVD_LOC_DEVICE = 0, TSVD_LOC_PINNED_HOST = 1 } tsvd_loc;
+
+/* How the Gram (Algorithm 2's B = X^T X or X X^T) is computed.
+ * FP32:   FP32 operands, FP32 MFMA, FP32 accumulation.
+ * BF16X3: each FP32 element a is split into hi = bf16(a), lo = bf16(a - hi);
+ *         the Gram is hi^T hi + hi^T lo + lo^T hi on BF16 MFMA with FP32
+ *         accumulation (lo^T lo is dropped).  Same HBM traffic as FP32.
+ * FP64:   FP64 operands and accumulation (FP64 MFMA); requires FP64 A.
+ * AUTO:   FP64 for FP64 A, BF16X3 for FP32 A.                               */
+typedef enum { TSVD_GRAM_AUTO = 0, TSVD_GRAM_FP32 = 1, TSVD_GRAM_BF16X3 = 2, TSVD_GRAM_FP64 = 3 } tsvd_gram;
+
+/* Which Gram: RIGHT = A^T A (n x n, iterate on v), LEFT = A A^T (m x m, iterate on u). */
+typedef enum { TSVD_SIDE_RIGHT = 0, TSVD_SIDE_LEFT = 1 } tsvd_side;
+
+typedef struct {
+  int32_t k;               /* triplets wanted; -1 = min(m, n) (Algorithm 1) */
+  double eps;              /* stopping test |v0 . v1| >= 1 - eps of Algorithm 2, evaluated in FP64;
+                              eps <= 0 runs exactly max_iter iterations per triplet */
+  int32_t max_iter;        /* iteration cap per triplet (the paper's loop has none); default 10000 */
+  const int32_t* fixed_iters; /* optional HOST array of k counts: triplet l runs exactly fixed_iters[l]
+                                 iterations (trajectory mode); overrides eps */
+  const double* v0;        /* DEVICE, k x d row-major, d = length of the iterated vector (n for the
+                              right branch, m for the left): row l is the N(0, I) start vector of
+                              triplet l (Algorithm 2 draws one per call).  Required. */
+  int32_t gram;            /* tsvd_gram */
+  int64_t rows_per_block;  /* contraction rows per Gram chunk (in HBM) or per streamed batch
+                              (pinned host); 0 = library default */
+  int64_t hbm_budget;      /* device bytes the call may allocate for workspace; 0 = no limit */
+  int32_t branch;          /* 0: m >= n iterates on v (A^T A); 1: m > n as printed in Algorithm 1 */
+  int32_t queue_depth;     /* device buffers in the host->device batch pipeline (>= 2; default 2) */
+} tsvd_opts;
+
+typedef struct {
+  int32_t k_done;          /* triplets computed before a zero product stopped the run */
+  int32_t rank_deficient;  /* 1 if a zero product or sigma = 0 was met */
+  int32_t converged;       /* 1 if every triplet met the stopping test (always 1 in fixed modes) */
+  int32_t branch_right;    /* 1: v first on A^T A; 0: u first on A A^T */
+  int32_t* iters;          /* optional HOST array of k: iterations taken per triplet (filled) */
+  double* lambda;          /* optional HOST array of k: ||B_l x|| at the last iteration (filled) */
+  double t_gram_ms;        /* device time of the Gram phase (HIP events) */
+  double t_eig_ms;         /* device time of the power-iteration phase */
+  double t_final_ms;       /* device time of the FP64 finishing pass (U = A V / sigma, signs) */
+  double t_total_ms;       /* device time of the whole call */
+  int64_t workspace_bytes; /* device workspace the call used */
+  int64_t h2d_bytes;       /* bytes copied host -> device (pinned-host input) */
+} tsvd_info;
+
+typedef struct tsvd_ctx tsvd_ctx;
+
+/* Create a context on HIP device `device`.  Queries the device (CU count,
+ * LDS size) and creates the library's internal streams.  Returns
+ * INVALID_ARG for a bad device, HIP on runtime failure. */
+tsvd_status tsvd_ctx_create(int device, tsvd_ctx** out);
+
+/* Destroy a context and free its workspaces.  NULL is ignored. */
+void tsvd_ctx_destroy(tsvd_ctx* ctx);
+
+/* Static string for a status code. */
+const char* tsvd_status_string(tsvd_status s);
+
+/* Message of the last failing call on `ctx` ("" if none).  Owned by ctx. */
+const char* tsvd_last_error(const tsvd_ctx* ctx);
+
+/* Fill opts with defaults: k = -1, eps = 1e-8, max_iter = 10000, gram = AUTO,
+ * everything else 0/NULL, queue_depth = 2. */
+void tsvd_opts_default(tsvd_opts* opts);
+
+/* ---------------------------------------------------------------------------
+ * Step entry points (each is one row of the method; tsvd_dense chains them)
+ * ------------------------------------------------------------------------- */
+
+/* Gram product, Algorithm 2's B = X^T X (side RIGHT) or X X^T (side LEFT),
+ * formed as Algorithm 3's sum of block products over chunks of the
+ * contraction dimension.  A: DEVICE, dtype, m x n row-major (lda).  B: DEVICE,
+ * d x d (d = n for RIGHT, m for LEFT) row-major (ldb), FP32 for gram FP32 /
+ * BF16X3, FP64 for gram FP64; both triangles are written.  accumulate != 0
+ * adds to B (B += A^T A) instead of overwriting it.  rows_per_block: chunk of
+ * the contraction dimension per work unit (0 = default).  Asynchronous. */
+tsvd_status tsvd_gram_dense(tsvd_ctx* ctx, const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
+                            int32_t gram, int32_t side, int64_t rows_per_block, void* B, int64_t ldb,
+                            int32_t accumulate, void* stream);
+
+/* Power iteration with deflation on a symmetric d x d Gram (Algorithm 2, run
+ * for l = 1..k as Algorithm 1 does).  B: DEVICE, row-major (ldb), dtype FP32
+ * or FP64; it is OVERWRITTEN by the deflated Gram (I - v v^T) B (I - v v^T)
+ * after each triplet.  opts->v0 (k x d start vectors), k, eps, max_iter,
+ * fixed_iters apply.  X: DEVICE FP64 d x k column-major (ldx): the unit
+ * iterate vectors, re-orthogonalised in FP64 against the earlier columns.
+ * Synchronises `stream`; fills info (k_done, converged, iters, lambda). */
+tsvd_status tsvd_power_gram(tsvd_ctx* ctx, void* B, int32_t dtype, int64_t d, int64_t ldb,
+                            const tsvd_opts* opts, double* X, int64_t ldx, tsvd_info* info, void* stream);
+
+/* Finishing pass of Algorithm 1 for all k triplets at once, in FP64:
+ * W = A X (side RIGHT: X is n x k, W is m x k) or W = A^T X (side LEFT: X is
+ * m x k, W is n x k); S[j] = ||W[:, j]||; W[:, j] /= S[j] (columns with
+ * S[j] = 0 are left zero).  A: DEVICE dtype row-major (lda); X, W: DEVICE FP64
+ * column-major; S: DEVICE FP64 k.  Asynchronous. */
+tsvd_status tsvd_finish_dense(tsvd_ctx* ctx, const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
+                              int32_t side, const double* X, int64_t ldx, int32_t k, double* W, int64_t ldw,
+                              double* S, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Whole t-SVD (Algorithm 1), dense A
+ * ------------------------------------------------------------------------- */
+
+/* A: dtype, m x n row-major (lda); loc DEVICE (in HBM) or PINNED_HOST (pinned
+ * host memory, streamed to the device in row batches through a
+ * double-buffered copy pipeline; FP32 only).  U: DEVICE FP64 m x k
+ * column-major (ldu); S: DEVICE FP64 k; V: DEVICE FP64 n x k column-major
+ * (ldv).  Triplets past info->k_done are zero.  Synchronises `stream`.
+ * Returns OK, NOT_CONVERGED (outputs filled), NONFINITE, INVALID_ARG,
+ * OUT_OF_MEMORY, UNSUPPORTED or HIP. */
+tsvd_status tsvd_dense(tsvd_ctx* ctx, const void* A, int32_t dtype, int32_t loc, int64_t m, int64_t n,
+                       int64_t lda, const tsvd_opts* opts, double* U, int64_t ldu, double* S, double* V,
+                       int64_t ldv, tsvd_info* info, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TSVD_H */

@@ -78,6 +78,8 @@ __all__ = [
     "eq3_apply",
     "alg4_compute_v0",
     "alg3_gram_tasks",
+    "bf16_round",
+    "gram_bf16x3",
     "canonical",
     "subspace_angles",
 ]
@@ -181,6 +183,34 @@ def alg3_gram_tasks(A: np.ndarray, n_b: int) -> np.ndarray:
             B[i0:i1, j0:j1] = Bij
             B[j0:j1, i0:i1] = Bij.T
     return B
+
+
+def bf16_round(x) -> np.ndarray:
+    """Round float32 values to bfloat16 (round to nearest, ties to even),
+    returned as float32.  bfloat16 keeps the top 16 bits of the float32
+    pattern; rounding adds 0x7FFF plus the lowest kept bit before truncating.
+    (Finite inputs only.)"""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    b = x.view(np.uint32).astype(np.uint64)
+    b = (b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000
+    return b.astype(np.uint32).view(np.float32)
+
+
+def gram_bf16x3(A: np.ndarray, side: str = "right") -> np.ndarray:
+    """The Gram of the BF16X3 precision mode, by definition.
+
+    Every FP32 element is split as hi = bf16(a), lo = bf16(a - hi) (a - hi is
+    exact in FP32), and B = hi^T hi + hi^T lo + lo^T hi (lo^T lo dropped),
+    here accumulated in float64.  side 'left' gives the A A^T analogue.
+    """
+    a = np.asarray(A, dtype=np.float32)
+    hi = bf16_round(a)
+    lo = bf16_round(a - hi)
+    h = hi.astype(np.float64)
+    l_ = lo.astype(np.float64)
+    if side == "right":
+        return h.T @ h + h.T @ l_ + l_.T @ h
+    return h @ h.T + h @ l_.T + l_ @ h.T
 
 
 # ----------------------------------------------------------------------------

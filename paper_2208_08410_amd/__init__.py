@@ -1,0 +1,331 @@
+"""Truncated SVD by the power method on MI355X (gfx950): Python binding.
+
+A thin ctypes layer over libtsvd.so (declared in include/tsvd.h).  Functions
+keep the C names and only marshal arguments: torch tensors supply device
+memory and the current HIP stream; every step of the computation runs in the
+library's HIP kernels.  There is no fallback: if the library is not built, or
+no GPU is present, the calls raise.
+
+Layouts follow the C ABI: A is row-major; U (m x k) and V (n x k) come back as
+column-major matrices, i.e. torch views ``t.T`` of contiguous (k, m) / (k, n)
+tensors, so column j is contiguous; S is float64.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = [
+    "TsvdError",
+    "Context",
+    "load_library",
+    "library_path",
+    "STATUS",
+    "tsvd_gram_dense",
+    "tsvd_power_gram",
+    "tsvd_finish_dense",
+    "tsvd_dense",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_NAME = "libtsvd.so"
+
+STATUS = {
+    0: "TSVD_OK",
+    1: "TSVD_ERR_INVALID_ARG",
+    2: "TSVD_ERR_OUT_OF_MEMORY",
+    3: "TSVD_ERR_NOT_CONVERGED",
+    4: "TSVD_ERR_NONFINITE",
+    5: "TSVD_ERR_HIP",
+    6: "TSVD_ERR_REJECTED",
+    7: "TSVD_ERR_UNSUPPORTED",
+    8: "TSVD_ERR_INTERNAL",
+}
+OK, INVALID_ARG, OUT_OF_MEMORY, NOT_CONVERGED, NONFINITE, HIP, REJECTED, UNSUPPORTED, INTERNAL = range(9)
+
+F32, F64 = 0, 1
+LOC_DEVICE, LOC_PINNED_HOST = 0, 1
+GRAM = {"auto": 0, "fp32": 1, "bf16x3": 2, "fp64": 3}
+SIDE = {"right": 0, "left": 1}
+
+
+class TsvdError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+        super().__init__(f"{self.name}: {message}")
+
+
+class TsvdOpts(ctypes.Structure):
+    _fields_ = [
+        ("k", ctypes.c_int32),
+        ("eps", ctypes.c_double),
+        ("max_iter", ctypes.c_int32),
+        ("fixed_iters", ctypes.POINTER(ctypes.c_int32)),
+        ("v0", ctypes.c_void_p),
+        ("gram", ctypes.c_int32),
+        ("rows_per_block", ctypes.c_int64),
+        ("hbm_budget", ctypes.c_int64),
+        ("branch", ctypes.c_int32),
+        ("queue_depth", ctypes.c_int32),
+    ]
+
+
+class TsvdInfo(ctypes.Structure):
+    _fields_ = [
+        ("k_done", ctypes.c_int32),
+        ("rank_deficient", ctypes.c_int32),
+        ("converged", ctypes.c_int32),
+        ("branch_right", ctypes.c_int32),
+        ("iters", ctypes.POINTER(ctypes.c_int32)),
+        ("lambda_", ctypes.POINTER(ctypes.c_double)),
+        ("t_gram_ms", ctypes.c_double),
+        ("t_eig_ms", ctypes.c_double),
+        ("t_final_ms", ctypes.c_double),
+        ("t_total_ms", ctypes.c_double),
+        ("workspace_bytes", ctypes.c_int64),
+        ("h2d_bytes", ctypes.c_int64),
+    ]
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return os.path.join(_HERE, _LIB_NAME)
+
+
+def load_library():
+    """Load libtsvd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = library_path()
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2208_08410_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    lib.tsvd_ctx_create.argtypes = [ctypes.c_int, ctypes.POINTER(vp)]
+    lib.tsvd_ctx_create.restype = ctypes.c_int
+    lib.tsvd_ctx_destroy.argtypes = [vp]
+    lib.tsvd_ctx_destroy.restype = None
+    lib.tsvd_status_string.argtypes = [ctypes.c_int]
+    lib.tsvd_status_string.restype = ctypes.c_char_p
+    lib.tsvd_last_error.argtypes = [vp]
+    lib.tsvd_last_error.restype = ctypes.c_char_p
+    lib.tsvd_opts_default.argtypes = [ctypes.POINTER(TsvdOpts)]
+    lib.tsvd_opts_default.restype = None
+    lib.tsvd_gram_dense.argtypes = [vp, vp, i32, i64, i64, i64, i32, i32, i64, vp, i64, i32, vp]
+    lib.tsvd_gram_dense.restype = ctypes.c_int
+    lib.tsvd_power_gram.argtypes = [vp, vp, i32, i64, i64, ctypes.POINTER(TsvdOpts), vp, i64,
+                                    ctypes.POINTER(TsvdInfo), vp]
+    lib.tsvd_power_gram.restype = ctypes.c_int
+    lib.tsvd_finish_dense.argtypes = [vp, vp, i32, i64, i64, i64, i32, vp, i64, i32, vp, i64, vp, vp]
+    lib.tsvd_finish_dense.restype = ctypes.c_int
+    lib.tsvd_dense.argtypes = [vp, vp, i32, i32, i64, i64, i64, ctypes.POINTER(TsvdOpts), vp, i64, vp, vp, i64,
+                               ctypes.POINTER(TsvdInfo), vp]
+    lib.tsvd_dense.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Context:
+    """Owns a tsvd_ctx on one device."""
+
+    def __init__(self, device: int = 0):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device is visible: the t-SVD library runs on the GPU only")
+        self.lib = load_library()
+        self.device = device
+        h = ctypes.c_void_p()
+        st = self.lib.tsvd_ctx_create(device, ctypes.byref(h))
+        if st != OK:
+            raise TsvdError(st, f"tsvd_ctx_create({device}) failed")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.tsvd_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def last_error(self) -> str:
+        return self.lib.tsvd_last_error(self.handle).decode()
+
+    def check(self, st: int, allow=(OK,)):
+        if st not in allow:
+            raise TsvdError(st, self.last_error())
+        return st
+
+
+def _stream(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype == torch.float64:
+        return F64
+    raise TypeError(f"A must be float32 or float64, got {t.dtype}")
+
+
+def _rowmajor(A):
+    if A.dim() != 2 or A.stride(1) != 1 or A.stride(0) < A.shape[1]:
+        raise ValueError("A must be a 2-D row-major tensor (stride(1) == 1, stride(0) >= n)")
+    return A.shape[0], A.shape[1], A.stride(0)
+
+
+def _colmajor_out(rows: int, k: int, device, dtype=None):
+    torch = _torch()
+    t = torch.zeros((k, rows), dtype=dtype or torch.float64, device=device)
+    return t.T  # rows x k, column-major
+
+
+def _make_opts(lib, k, eps, v0, max_iter, fixed_iters, gram, rows_per_block, hbm_budget, branch):
+    o = TsvdOpts()
+    lib.tsvd_opts_default(ctypes.byref(o))
+    o.k = int(k)
+    o.eps = float(eps)
+    o.max_iter = int(max_iter)
+    keep = None
+    if fixed_iters is not None:
+        arr = (ctypes.c_int32 * len(fixed_iters))(*[int(x) for x in fixed_iters])
+        o.fixed_iters = ctypes.cast(arr, ctypes.POINTER(ctypes.c_int32))
+        keep = arr
+    o.v0 = ctypes.c_void_p(v0.data_ptr()) if v0 is not None else None
+    o.gram = GRAM[gram] if isinstance(gram, str) else int(gram)
+    o.rows_per_block = int(rows_per_block)
+    o.hbm_budget = int(hbm_budget)
+    o.branch = int(branch)
+    return o, keep
+
+
+def _info_dict(info: TsvdInfo, it, lam, k, status):
+    return {
+        "status": STATUS.get(status, status),
+        "k_done": info.k_done,
+        "rank_deficient": bool(info.rank_deficient),
+        "converged": bool(info.converged),
+        "branch_right": bool(info.branch_right),
+        "iters": [it[i] for i in range(k)],
+        "lambda": [lam[i] for i in range(k)],
+        "t_gram_ms": info.t_gram_ms,
+        "t_eig_ms": info.t_eig_ms,
+        "t_final_ms": info.t_final_ms,
+        "t_total_ms": info.t_total_ms,
+        "workspace_bytes": info.workspace_bytes,
+        "h2d_bytes": info.h2d_bytes,
+    }
+
+
+def _check_v0(v0, k, d, device):
+    torch = _torch()
+    if v0 is None:
+        raise ValueError("v0 (k x d start vectors, float64 on the device) is required")
+    if v0.dtype != torch.float64 or v0.device != device or not v0.is_contiguous() or tuple(v0.shape) != (k, d):
+        raise ValueError(f"v0 must be a contiguous float64 ({k}, {d}) tensor on {device}")
+
+
+def tsvd_gram_dense(ctx: Context, A, gram="bf16x3", side="right", rows_per_block=0, B=None, accumulate=False,
+                    stream=None):
+    """B = A^T A (side 'right') or A A^T ('left'), both triangles, on the device."""
+    torch = _torch()
+    m, n, lda = _rowmajor(A)
+    d = n if side == "right" else m
+    gcode = GRAM[gram] if isinstance(gram, str) else int(gram)
+    bdt = torch.float64 if gcode == GRAM["fp64"] or (gcode == 0 and A.dtype == torch.float64) else torch.float32
+    if B is None:
+        B = torch.zeros((d, d), dtype=bdt, device=A.device)
+    st = ctx.lib.tsvd_gram_dense(ctx.handle, ctypes.c_void_p(A.data_ptr()), _dtype_code(A), m, n, lda, gcode,
+                                 SIDE[side], int(rows_per_block), ctypes.c_void_p(B.data_ptr()), B.stride(0),
+                                 1 if accumulate else 0, _stream(stream))
+    ctx.check(st)
+    return B
+
+
+def tsvd_power_gram(ctx: Context, B, k, eps, v0, max_iter=10000, fixed_iters=None, stream=None):
+    """Power iteration with deflation on the symmetric B (overwritten by the
+    deflated Gram).  Returns (X [d x k] column-major float64, info)."""
+    torch = _torch()
+    d = B.shape[0]
+    kk = d if k == -1 else k
+    _check_v0(v0, kk, d, B.device)
+    X = _colmajor_out(d, kk, B.device)
+    o, keep = _make_opts(ctx.lib, k, eps, v0, max_iter, fixed_iters, "auto", 0, 0, 0)
+    it = (ctypes.c_int32 * kk)()
+    lam = (ctypes.c_double * kk)()
+    info = TsvdInfo()
+    info.iters = ctypes.cast(it, ctypes.POINTER(ctypes.c_int32))
+    info.lambda_ = ctypes.cast(lam, ctypes.POINTER(ctypes.c_double))
+    st = ctx.lib.tsvd_power_gram(ctx.handle, ctypes.c_void_p(B.data_ptr()), _dtype_code(B), d, B.stride(0),
+                                 ctypes.byref(o), ctypes.c_void_p(X.data_ptr()), X.stride(1), ctypes.byref(info),
+                                 _stream(stream))
+    ctx.check(st, allow=(OK, NOT_CONVERGED))
+    del keep
+    return X, _info_dict(info, it, lam, kk, st)
+
+
+def tsvd_finish_dense(ctx: Context, A, side, X, k, stream=None):
+    """W = A X ('right') or A^T X ('left') in FP64, S = column norms, W /= S."""
+    torch = _torch()
+    m, n, lda = _rowmajor(A)
+    M = m if side == "right" else n
+    W = _colmajor_out(M, k, A.device)
+    S = torch.zeros(k, dtype=torch.float64, device=A.device)
+    if X.stride(0) != 1:
+        raise ValueError("X must be column-major (stride(0) == 1)")
+    st = ctx.lib.tsvd_finish_dense(ctx.handle, ctypes.c_void_p(A.data_ptr()), _dtype_code(A), m, n, lda, SIDE[side],
+                                   ctypes.c_void_p(X.data_ptr()), X.stride(1), int(k), ctypes.c_void_p(W.data_ptr()),
+                                   W.stride(1), ctypes.c_void_p(S.data_ptr()), _stream(stream))
+    ctx.check(st)
+    return W, S
+
+
+def tsvd_dense(ctx: Context, A, k, eps, v0, max_iter=10000, fixed_iters=None, gram="auto", rows_per_block=0,
+               hbm_budget=0, branch=0, stream=None, raise_not_converged=False):
+    """Whole t-SVD of a dense A (device tensor).  Returns (U, S, V, info) with
+    U (m x k) and V (n x k) column-major float64 and S float64."""
+    torch = _torch()
+    m, n, lda = _rowmajor(A)
+    kk = min(m, n) if k == -1 else k
+    right = (m > n) if branch == 1 else (m >= n)
+    d = n if right else m
+    _check_v0(v0, kk, d, A.device)
+    U = _colmajor_out(m, kk, A.device)
+    V = _colmajor_out(n, kk, A.device)
+    S = torch.zeros(kk, dtype=torch.float64, device=A.device)
+    o, keep = _make_opts(ctx.lib, k, eps, v0, max_iter, fixed_iters, gram, rows_per_block, hbm_budget, branch)
+    it = (ctypes.c_int32 * kk)()
+    lam = (ctypes.c_double * kk)()
+    info = TsvdInfo()
+    info.iters = ctypes.cast(it, ctypes.POINTER(ctypes.c_int32))
+    info.lambda_ = ctypes.cast(lam, ctypes.POINTER(ctypes.c_double))
+    st = ctx.lib.tsvd_dense(ctx.handle, ctypes.c_void_p(A.data_ptr()), _dtype_code(A), LOC_DEVICE, m, n, lda,
+                            ctypes.byref(o), ctypes.c_void_p(U.data_ptr()), U.stride(1), ctypes.c_void_p(S.data_ptr()),
+                            ctypes.c_void_p(V.data_ptr()), V.stride(1), ctypes.byref(info), _stream(stream))
+    ctx.check(st, allow=(OK,) if raise_not_converged else (OK, NOT_CONVERGED))
+    del keep
+    return U, S, V, _info_dict(info, it, lam, kk, st)

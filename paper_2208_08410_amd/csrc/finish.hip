@@ -1,0 +1,226 @@
+// Finishing pass of Algorithm 1 for all triplets at once, in FP64:
+//   side RIGHT: U_raw = A V      (u = A v, sigma = ||u||, u = u / sigma)
+//   side LEFT:  V_raw = A^T U    (v = A^T u, sigma = ||v||, v = v / sigma)
+// The product runs on v_mfma_f64_16x16x4f64; each workgroup also emits the
+// partial column sums of squares of its rows, which a second kernel adds in
+// workgroup order (deterministic) to give sigma.  A last kernel divides by
+// sigma and applies the sign convention (largest-|.| entry of each v positive).
+#include "common.h"
+#include "internal.h"
+
+namespace tsvd {
+
+constexpr int FBM = 128;  // output rows per workgroup
+constexpr int FBN = 64;   // output columns per workgroup
+constexpr int FBK = 16;   // contraction per stage
+constexpr int FLDK = FBK + 2;
+
+__device__ __forceinline__ int kpos4(int k) { return (k & 3) * 4 + (k >> 2); }
+
+// W[M x N] (column-major, ldw) = op(A) X, X is K x N column-major (ldx).
+// side 0: op(A) = A (M = m, K = n); side 1: op(A) = A^T (M = n, K = m).
+template <typename AT, int SIDE>
+__global__ __launch_bounds__(256) void finish_gemm_kernel(const AT* A, int64_t lda, int64_t M, int64_t K,
+                                                          const double* X, int64_t ldx, int N, double* W,
+                                                          int64_t ldw, double* ssq) {
+  __shared__ double As[2][FBM * FLDK];
+  __shared__ double Xs[2][FBN * FLDK];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t m0 = (int64_t)blockIdx.x * FBM;
+  const int j0 = blockIdx.y * FBN;
+  const int nk = (int)((K + FBK - 1) / FBK);
+
+  double av[8], xv[4];
+  auto load = [&](int kt) {
+    const int64_t k0 = (int64_t)kt * FBK;
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
+      const int f = tid + 256 * e;
+      int r, kk;
+      if (SIDE == 0) { kk = f % FBK; r = f / FBK; }
+      else { r = f % FBM; kk = f / FBM; }
+      const int64_t gr = m0 + r, gk = k0 + kk;
+      av[e] = (gr < M && gk < K) ? (double)(SIDE == 0 ? A[gr * lda + gk] : A[gk * lda + gr]) : 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+      const int f = tid + 256 * e;
+      const int kk = f % FBK, j = f / FBK;
+      const int64_t gk = k0 + kk;
+      xv[e] = (gk < K && j0 + j < N) ? X[(int64_t)(j0 + j) * ldx + gk] : 0.0;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
+      const int f = tid + 256 * e;
+      int r, kk;
+      if (SIDE == 0) { kk = f % FBK; r = f / FBK; }
+      else { r = f % FBM; kk = f / FBM; }
+      As[buf][r * FLDK + kpos4(kk)] = av[e];
+    }
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+      const int f = tid + 256 * e;
+      const int kk = f % FBK, j = f / FBK;
+      Xs[buf][j * FLDK + kpos4(kk)] = xv[e];
+    }
+  };
+
+  doublex4 acc[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; i++)
+#pragma unroll
+    for (int j = 0; j < 4; j++)
+#pragma unroll
+      for (int e = 0; e < 4; e++) acc[i][j][e] = 0.0;
+
+  if (nk > 0) { load(0); store(0); }
+  __syncthreads();
+  const int q = lane >> 4;
+  for (int kt = 0; kt < nk; kt++) {
+    const int cur = kt & 1;
+    const bool more = kt + 1 < nk;
+    if (more) load(kt + 1);
+#pragma unroll
+    for (int s = 0; s < 4; s++) {
+      double a[2], x[4];
+#pragma unroll
+      for (int i = 0; i < 2; i++) a[i] = As[cur][(wave * 32 + i * 16 + (lane & 15)) * FLDK + q * 4 + s];
+#pragma unroll
+      for (int j = 0; j < 4; j++) x[j] = Xs[cur][(j * 16 + (lane & 15)) * FLDK + q * 4 + s];
+#pragma unroll
+      for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], x[j], acc[i][j], 0, 0, 0);
+    }
+    if (more) store(cur ^ 1);
+    __syncthreads();
+  }
+
+  // write W and the per-column sums of squares of this row tile
+  __shared__ double colss[4][FBN];
+  double ss[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int i = 0; i < 2; i++)
+#pragma unroll
+    for (int j = 0; j < 4; j++)
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        const int64_t r = m0 + wave * 32 + i * 16 + 4 * e + (lane >> 4);
+        const int c = j0 + j * 16 + (lane & 15);
+        const double v = acc[i][j][e];
+        if (r < M && c < N) {
+          W[(int64_t)c * ldw + r] = v;
+          ss[j] = fma(v, v, ss[j]);
+        }
+      }
+#pragma unroll
+  for (int j = 0; j < 4; j++) {
+    double v = ss[j];
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    if (lane < 16) colss[wave][j * 16 + lane] = v;
+  }
+  __syncthreads();
+  if (tid < FBN && j0 + tid < N) {
+    const double t = colss[0][tid] + colss[1][tid] + colss[2][tid] + colss[3][tid];
+    ssq[(int64_t)blockIdx.x * N + j0 + tid] = t;
+  }
+}
+
+// sigma_j = sqrt(sum over row tiles of ssq[b][j]), added in tile order.
+__global__ void finish_sigma_kernel(const double* ssq, int nb, int N, double* S) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  double t = 0.0;
+  for (int b = 0; b < nb; b++) t += ssq[(int64_t)b * N + j];
+  S[j] = sqrt(t);
+}
+
+// Column j: divide W[:, j] by S[j] (zero columns stay zero), then find the
+// largest-|.| entry of V[:, j] (ties: lowest index) and flip V[:, j] and
+// U[:, j] if it is negative.  W aliases U (side RIGHT) or V (side LEFT).
+__global__ __launch_bounds__(256) void finish_scale_sign_kernel(double* W, int64_t ldw, int64_t Mw, const double* S,
+                                                                double* V, int64_t ldv, int64_t n, double* U,
+                                                                int64_t ldu, int64_t m, int do_sign) {
+  const int j = blockIdx.x;
+  const int tid = threadIdx.x;
+  const double s = S[j];
+  const double inv = s > 0.0 ? 1.0 / s : 0.0;
+  double* w = W + (int64_t)j * ldw;
+  for (int64_t i = tid; i < Mw; i += 256) w[i] = s > 0.0 ? w[i] * inv : 0.0;
+  if (!do_sign) return;
+  __syncthreads();
+  const double* v = V + (int64_t)j * ldv;
+  double best = -1.0;
+  int64_t bi = 0;
+  for (int64_t i = tid; i < n; i += 256) {
+    const double a = fabs(v[i]);
+    if (a > best) { best = a; bi = i; }
+  }
+  __shared__ double sb[256];
+  __shared__ int64_t si[256];
+  sb[tid] = best; si[tid] = bi;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (tid < off) {
+      const double ob = sb[tid + off];
+      const int64_t oi = si[tid + off];
+      if (ob > sb[tid] || (ob == sb[tid] && oi < si[tid])) { sb[tid] = ob; si[tid] = oi; }
+    }
+    __syncthreads();
+  }
+  const bool flip = V[(int64_t)j * ldv + si[0]] < 0.0;
+  __syncthreads();
+  if (flip) {
+    double* vv = V + (int64_t)j * ldv;
+    double* uu = U + (int64_t)j * ldu;
+    for (int64_t i = tid; i < n; i += 256) vv[i] = -vv[i];
+    for (int64_t i = tid; i < m; i += 256) uu[i] = -uu[i];
+  }
+}
+
+int finish_workspace_doubles(int64_t m, int64_t n, int side, int k) {
+  const int64_t M = side == 0 ? m : n;
+  const int64_t nb = (M + FBM - 1) / FBM;
+  return (int)(nb * k);
+}
+
+int finish_launch(int is_f64, int side, const void* A, int64_t m, int64_t n, int64_t lda, const double* X,
+                  int64_t ldx, int k, double* W, int64_t ldw, double* S, double* ssq, hipStream_t stream) {
+  const int64_t M = side == 0 ? m : n;
+  const int64_t K = side == 0 ? n : m;
+  const int64_t nb = (M + FBM - 1) / FBM;
+  dim3 grid((unsigned)nb, (unsigned)((k + FBN - 1) / FBN));
+  if (is_f64) {
+    if (side == 0)
+      hipLaunchKernelGGL((finish_gemm_kernel<double, 0>), grid, dim3(256), 0, stream, (const double*)A, lda, M, K, X,
+                         ldx, k, W, ldw, ssq);
+    else
+      hipLaunchKernelGGL((finish_gemm_kernel<double, 1>), grid, dim3(256), 0, stream, (const double*)A, lda, M, K, X,
+                         ldx, k, W, ldw, ssq);
+  } else {
+    if (side == 0)
+      hipLaunchKernelGGL((finish_gemm_kernel<float, 0>), grid, dim3(256), 0, stream, (const float*)A, lda, M, K, X,
+                         ldx, k, W, ldw, ssq);
+    else
+      hipLaunchKernelGGL((finish_gemm_kernel<float, 1>), grid, dim3(256), 0, stream, (const float*)A, lda, M, K, X,
+                         ldx, k, W, ldw, ssq);
+  }
+  TSVD_HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(finish_sigma_kernel, dim3((k + 127) / 128), dim3(128), 0, stream, ssq, (int)nb, k, S);
+  TSVD_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int finish_scale_sign_launch(double* W, int64_t ldw, int64_t Mw, const double* S, double* V, int64_t ldv, int64_t n,
+                             double* U, int64_t ldu, int64_t m, int k, int do_sign, hipStream_t stream) {
+  if (k <= 0) return 0;
+  hipLaunchKernelGGL(finish_scale_sign_kernel, dim3(k), dim3(256), 0, stream, W, ldw, Mw, S, V, ldv, n, U, ldu, m,
+                     do_sign);
+  TSVD_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+}  // namespace tsvd

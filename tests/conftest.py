@@ -16,3 +16,12 @@ def pytest_configure(config):
 def pytest_collection_modifyitems(config, items):
     # GPU tests run in one process on the box; nothing to reorder here beyond marking.
     pass
+
+
+@pytest.fixture(scope="session")
+def ctx():
+    """A library context on cuda:0 (GPU tests only)."""
+    import paper_2208_08410_amd as P
+    c = P.Context(0)
+    yield c
+    c.close()
