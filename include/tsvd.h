@@ -119,6 +119,20 @@ const char* tsvd_status_string(tsvd_status s);
 /* Message of the last failing call on `ctx` ("" if none).  Owned by ctx. */
 const char* tsvd_last_error(const tsvd_ctx* ctx);
 
+/* Launch-shape tuning of a context (chosen by the library when 0).  The
+ * autotuner (paper_2208_08410_amd.autotune) measures candidates per shape class
+ * and sets these before a call. */
+typedef struct {
+  int32_t gram_tile;     /* BF16X3 Gram tile edge: 0 (library choice), 128 or 256 */
+  int32_t gram_chunks;   /* contraction chunks (split-K) per Gram launch: 0 = library choice */
+  int32_t power_blocks;  /* workgroups of the power-iteration launch: 0 = one per CU */
+  int32_t reserved;
+} tsvd_tuning;
+
+/* Set / read the context's tuning.  INVALID_ARG for out-of-range values. */
+tsvd_status tsvd_ctx_set_tuning(tsvd_ctx* ctx, const tsvd_tuning* tuning);
+tsvd_status tsvd_ctx_get_tuning(const tsvd_ctx* ctx, tsvd_tuning* tuning);
+
 /* Fill opts with defaults: k = -1, eps = 1e-8, max_iter = 10000, gram = AUTO,
  * everything else 0/NULL, queue_depth = 2. */
 void tsvd_opts_default(tsvd_opts* opts);
@@ -171,6 +185,48 @@ tsvd_status tsvd_finish_dense(tsvd_ctx* ctx, const void* A, int32_t dtype, int64
 tsvd_status tsvd_dense(tsvd_ctx* ctx, const void* A, int32_t dtype, int32_t loc, int64_t m, int64_t n,
                        int64_t lda, const tsvd_opts* opts, double* U, int64_t ldu, double* S, double* V,
                        int64_t ldv, tsvd_info* info, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Sparse A (CSR): the implicit deflated product of Equation 2 / Algorithm 4
+ * ------------------------------------------------------------------------- */
+
+typedef struct tsvd_csr tsvd_csr;
+
+/* Register an m x n CSR matrix held on the device: rowptr int64 [m+1],
+ * col int32 [nnz] (0 <= col < n), val FP32 [nnz].  The arrays are BORROWED and
+ * must outlive the handle.  The structure is validated on the device first
+ * (monotone row pointers, rowptr[0] = 0, rowptr[m] = nnz, column range);
+ * a violation returns INVALID_ARG before any product reads through it.  Then
+ * the transpose is built once as a CSC copy owned by the handle (counting sort
+ * by column, rows ascending inside each column), so that both A x and A^T y
+ * are gather-only products.  Synchronises `stream`. */
+tsvd_status tsvd_csr_create(tsvd_ctx* ctx, int64_t m, int64_t n, int64_t nnz, const int64_t* rowptr,
+                            const int32_t* col, const float* val, tsvd_csr** out, void* stream);
+
+/* Free the handle's CSC copy.  NULL is ignored. */
+void tsvd_csr_destroy(tsvd_csr* csr);
+
+/* Copy the CSC transpose into caller DEVICE buffers: colptr int64 [n+1],
+ * rowidx int32 [nnz], val FP32 [nnz].  Asynchronous. */
+tsvd_status tsvd_csr_get_csc(tsvd_ctx* ctx, const tsvd_csr* csr, int64_t* colptr, int32_t* rowidx, float* val,
+                             void* stream);
+
+/* Sparse product with FP64 accumulation: trans = 0: y = A x (x: n entries,
+ * y: m entries); trans = 1: y = A^T x (x: m, y: n).  x DEVICE FP32 (x_dtype
+ * TSVD_F32) or FP64 (TSVD_F64); y DEVICE FP64.  Asynchronous. */
+tsvd_status tsvd_spmv(tsvd_ctx* ctx, const tsvd_csr* csr, int32_t trans, const void* x, int32_t x_dtype, double* y,
+                      void* stream);
+
+/* Whole t-SVD of a CSR matrix (Algorithm 1 with the implicit product of
+ * Algorithm 4 in factored form).  Each power iteration computes
+ * z = P A^T (A x) (right branch, m >= n) or z = P A (A^T x) (left branch):
+ * FP32 values, FP64 accumulation, FP64 projection P = I - V V^T against the
+ * triplets already found, with the start vector projected once.  Then
+ * u = A v / ||A v|| (or the mirror) in FP64.  opts->v0 is k x d (d = n right,
+ * m left).  U, S, V as in tsvd_dense.  Synchronises `stream` (one small
+ * device-to-host read per iteration for the stopping test). */
+tsvd_status tsvd_sparse(tsvd_ctx* ctx, const tsvd_csr* csr, const tsvd_opts* opts, double* U, int64_t ldu,
+                        double* S, double* V, int64_t ldv, tsvd_info* info, void* stream);
 
 #ifdef __cplusplus
 }

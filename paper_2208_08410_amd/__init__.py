@@ -26,6 +26,13 @@ __all__ = [
     "tsvd_power_gram",
     "tsvd_finish_dense",
     "tsvd_dense",
+    "set_tuning",
+    "get_tuning",
+    "Csr",
+    "tsvd_csr_create",
+    "tsvd_csr_get_csc",
+    "tsvd_spmv",
+    "tsvd_sparse",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -69,6 +76,15 @@ class TsvdOpts(ctypes.Structure):
         ("hbm_budget", ctypes.c_int64),
         ("branch", ctypes.c_int32),
         ("queue_depth", ctypes.c_int32),
+    ]
+
+
+class TsvdTuning(ctypes.Structure):
+    _fields_ = [
+        ("gram_tile", ctypes.c_int32),
+        ("gram_chunks", ctypes.c_int32),
+        ("power_blocks", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -126,6 +142,20 @@ def load_library():
     lib.tsvd_dense.argtypes = [vp, vp, i32, i32, i64, i64, i64, ctypes.POINTER(TsvdOpts), vp, i64, vp, vp, i64,
                                ctypes.POINTER(TsvdInfo), vp]
     lib.tsvd_dense.restype = ctypes.c_int
+    lib.tsvd_ctx_set_tuning.argtypes = [vp, ctypes.POINTER(TsvdTuning)]
+    lib.tsvd_ctx_set_tuning.restype = ctypes.c_int
+    lib.tsvd_ctx_get_tuning.argtypes = [vp, ctypes.POINTER(TsvdTuning)]
+    lib.tsvd_ctx_get_tuning.restype = ctypes.c_int
+    lib.tsvd_csr_create.argtypes = [vp, i64, i64, i64, vp, vp, vp, ctypes.POINTER(vp), vp]
+    lib.tsvd_csr_create.restype = ctypes.c_int
+    lib.tsvd_csr_destroy.argtypes = [vp]
+    lib.tsvd_csr_destroy.restype = None
+    lib.tsvd_csr_get_csc.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.tsvd_csr_get_csc.restype = ctypes.c_int
+    lib.tsvd_spmv.argtypes = [vp, vp, i32, vp, i32, vp, vp]
+    lib.tsvd_spmv.restype = ctypes.c_int
+    lib.tsvd_sparse.argtypes = [vp, vp, ctypes.POINTER(TsvdOpts), vp, i64, vp, vp, i64, ctypes.POINTER(TsvdInfo), vp]
+    lib.tsvd_sparse.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -174,6 +204,18 @@ class Context:
         if st not in allow:
             raise TsvdError(st, self.last_error())
         return st
+
+
+def set_tuning(ctx: Context, gram_tile: int = 0, gram_chunks: int = 0, power_blocks: int = 0):
+    """Set the context's launch-shape tuning (0 = library choice)."""
+    t = TsvdTuning(int(gram_tile), int(gram_chunks), int(power_blocks), 0)
+    ctx.check(ctx.lib.tsvd_ctx_set_tuning(ctx.handle, ctypes.byref(t)))
+
+
+def get_tuning(ctx: Context) -> dict:
+    t = TsvdTuning()
+    ctx.check(ctx.lib.tsvd_ctx_get_tuning(ctx.handle, ctypes.byref(t)))
+    return {"gram_tile": t.gram_tile, "gram_chunks": t.gram_chunks, "power_blocks": t.power_blocks}
 
 
 def _stream(stream):
@@ -305,27 +347,130 @@ def tsvd_finish_dense(ctx: Context, A, side, X, k, stream=None):
 
 
 def tsvd_dense(ctx: Context, A, k, eps, v0, max_iter=10000, fixed_iters=None, gram="auto", rows_per_block=0,
-               hbm_budget=0, branch=0, stream=None, raise_not_converged=False):
-    """Whole t-SVD of a dense A (device tensor).  Returns (U, S, V, info) with
-    U (m x k) and V (n x k) column-major float64 and S float64."""
+               hbm_budget=0, branch=0, stream=None, raise_not_converged=False, queue_depth=2):
+    """Whole t-SVD of a dense A.  A is a device tensor (resident in HBM) or a
+    pinned host tensor (``A.is_pinned()``: streamed in row batches).  Returns
+    (U, S, V, info) on the context's device, with U (m x k) and V (n x k)
+    column-major float64 and S float64."""
     torch = _torch()
     m, n, lda = _rowmajor(A)
     kk = min(m, n) if k == -1 else k
     right = (m > n) if branch == 1 else (m >= n)
     d = n if right else m
-    _check_v0(v0, kk, d, A.device)
-    U = _colmajor_out(m, kk, A.device)
-    V = _colmajor_out(n, kk, A.device)
-    S = torch.zeros(kk, dtype=torch.float64, device=A.device)
+    if A.is_cuda:
+        loc, dev = LOC_DEVICE, A.device
+    elif A.is_pinned():
+        loc, dev = LOC_PINNED_HOST, torch.device("cuda", ctx.device)
+    else:
+        raise ValueError("A must be a device tensor or a pinned host tensor")
+    _check_v0(v0, kk, d, dev)
+    U = _colmajor_out(m, kk, dev)
+    V = _colmajor_out(n, kk, dev)
+    S = torch.zeros(kk, dtype=torch.float64, device=dev)
     o, keep = _make_opts(ctx.lib, k, eps, v0, max_iter, fixed_iters, gram, rows_per_block, hbm_budget, branch)
+    o.queue_depth = int(queue_depth)
     it = (ctypes.c_int32 * kk)()
     lam = (ctypes.c_double * kk)()
     info = TsvdInfo()
     info.iters = ctypes.cast(it, ctypes.POINTER(ctypes.c_int32))
     info.lambda_ = ctypes.cast(lam, ctypes.POINTER(ctypes.c_double))
-    st = ctx.lib.tsvd_dense(ctx.handle, ctypes.c_void_p(A.data_ptr()), _dtype_code(A), LOC_DEVICE, m, n, lda,
+    st = ctx.lib.tsvd_dense(ctx.handle, ctypes.c_void_p(A.data_ptr()), _dtype_code(A), loc, m, n, lda,
                             ctypes.byref(o), ctypes.c_void_p(U.data_ptr()), U.stride(1), ctypes.c_void_p(S.data_ptr()),
                             ctypes.c_void_p(V.data_ptr()), V.stride(1), ctypes.byref(info), _stream(stream))
+    ctx.check(st, allow=(OK,) if raise_not_converged else (OK, NOT_CONVERGED))
+    del keep
+    return U, S, V, _info_dict(info, it, lam, kk, st)
+
+
+class Csr:
+    """A registered CSR matrix (device arrays are borrowed: this object keeps
+    references to them) plus the library's CSC copy."""
+
+    def __init__(self, ctx: Context, rowptr, col, val, shape, stream=None):
+        torch = _torch()
+        m, n = int(shape[0]), int(shape[1])
+        if rowptr.dtype != torch.int64 or col.dtype != torch.int32 or val.dtype != torch.float32:
+            raise TypeError("CSR arrays must be int64 rowptr, int32 col, float32 val")
+        for t in (rowptr, col, val):
+            if not t.is_cuda or not t.is_contiguous():
+                raise ValueError("CSR arrays must be contiguous device tensors")
+        if rowptr.numel() != m + 1 or col.numel() != val.numel():
+            raise ValueError("rowptr must have m + 1 entries and col/val the same length")
+        self.ctx, self.shape, self.nnz = ctx, (m, n), int(col.numel())
+        self._keep = (rowptr, col, val)
+        h = ctypes.c_void_p()
+        st = ctx.lib.tsvd_csr_create(ctx.handle, m, n, self.nnz, ctypes.c_void_p(rowptr.data_ptr()),
+                                     ctypes.c_void_p(col.data_ptr()), ctypes.c_void_p(val.data_ptr()), ctypes.byref(h),
+                                     _stream(stream))
+        ctx.check(st)
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.ctx.lib.tsvd_csr_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def tsvd_csr_create(ctx: Context, rowptr, col, val, shape, stream=None) -> Csr:
+    return Csr(ctx, rowptr, col, val, shape, stream)
+
+
+def tsvd_csr_get_csc(ctx: Context, csr: Csr, stream=None):
+    """(colptr int64 [n+1], rowidx int32 [nnz], val float32 [nnz]) of the CSC copy."""
+    torch = _torch()
+    dev = csr._keep[0].device
+    m, n = csr.shape
+    cp = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    ri = torch.empty(max(csr.nnz, 1), dtype=torch.int32, device=dev)
+    cv = torch.empty(max(csr.nnz, 1), dtype=torch.float32, device=dev)
+    st = ctx.lib.tsvd_csr_get_csc(ctx.handle, csr.handle, ctypes.c_void_p(cp.data_ptr()),
+                                  ctypes.c_void_p(ri.data_ptr()), ctypes.c_void_p(cv.data_ptr()), _stream(stream))
+    ctx.check(st)
+    return cp, ri[: csr.nnz], cv[: csr.nnz]
+
+
+def tsvd_spmv(ctx: Context, csr: Csr, x, trans: int = 0, stream=None):
+    """y = A x (trans 0) or A^T x (trans 1), FP64 accumulation; x float32 or float64."""
+    torch = _torch()
+    m, n = csr.shape
+    nin, nout = (n, m) if trans == 0 else (m, n)
+    if x.numel() != nin or not x.is_cuda or not x.is_contiguous():
+        raise ValueError(f"x must be a contiguous device vector of {nin} entries")
+    y = torch.empty(nout, dtype=torch.float64, device=x.device)
+    st = ctx.lib.tsvd_spmv(ctx.handle, csr.handle, int(trans), ctypes.c_void_p(x.data_ptr()), _dtype_code(x),
+                           ctypes.c_void_p(y.data_ptr()), _stream(stream))
+    ctx.check(st)
+    return y
+
+
+def tsvd_sparse(ctx: Context, csr: Csr, k, eps, v0, max_iter=10000, fixed_iters=None, branch=0, hbm_budget=0,
+                stream=None, raise_not_converged=False):
+    """Whole t-SVD of a registered CSR matrix.  Returns (U, S, V, info)."""
+    torch = _torch()
+    m, n = csr.shape
+    kk = min(m, n) if k == -1 else k
+    right = (m > n) if branch == 1 else (m >= n)
+    d = n if right else m
+    dev = csr._keep[0].device
+    _check_v0(v0, kk, d, dev)
+    U = _colmajor_out(m, kk, dev)
+    V = _colmajor_out(n, kk, dev)
+    S = torch.zeros(kk, dtype=torch.float64, device=dev)
+    o, keep = _make_opts(ctx.lib, k, eps, v0, max_iter, fixed_iters, "auto", 0, hbm_budget, branch)
+    it = (ctypes.c_int32 * kk)()
+    lam = (ctypes.c_double * kk)()
+    info = TsvdInfo()
+    info.iters = ctypes.cast(it, ctypes.POINTER(ctypes.c_int32))
+    info.lambda_ = ctypes.cast(lam, ctypes.POINTER(ctypes.c_double))
+    st = ctx.lib.tsvd_sparse(ctx.handle, csr.handle, ctypes.byref(o), ctypes.c_void_p(U.data_ptr()), U.stride(1),
+                             ctypes.c_void_p(S.data_ptr()), ctypes.c_void_p(V.data_ptr()), V.stride(1),
+                             ctypes.byref(info), _stream(stream))
     ctx.check(st, allow=(OK,) if raise_not_converged else (OK, NOT_CONVERGED))
     del keep
     return U, S, V, _info_dict(info, it, lam, kk, st)

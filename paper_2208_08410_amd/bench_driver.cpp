@@ -1,0 +1,173 @@
+// Stand-alone driver for profiling the dense t-SVD through the C ABI, without
+// Python in the process (rocprofv3 runs it directly).
+//
+//   tsvd_bench [m n k eps gram steps warmup seed]
+//     gram: 1 = FP32, 2 = BF16X3
+//   tsvd_bench copy BYTES [reps]
+//     a plain device-to-device copy kernel of BYTES (multiple of 16), the
+//     reference for scaling hardware traffic counters to bytes
+//
+// A = H_L [diag(s); 0] H_R with s_i = 0.97^i and H_L, H_R products of two
+// random Householder reflectors (exactly orthogonal), so the singular values
+// are s; start vectors are N(0, 1) from a counter-based generator.  Prints one
+// JSON line with per-step and per-phase times and the sigma error.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+
+#include <chrono>
+#include <vector>
+
+#include "../include/tsvd.h"
+
+static uint64_t splitmix(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+static double gauss(uint64_t seed, uint64_t i) {  // Box-Muller on two counter draws
+  const double u1 = ((splitmix(seed * 0x100000001B3ull + 2 * i) >> 11) + 1.0) * (1.0 / 9007199254740993.0);
+  const double u2 = (splitmix(seed * 0x100000001B3ull + 2 * i + 1) >> 11) * (1.0 / 9007199254740992.0);
+  return sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+}
+
+__global__ void copy_kernel(const float4* __restrict__ src, float4* __restrict__ dst, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+static int run_copy(size_t bytes, int reps) {
+  if (bytes == 0 || bytes % 16) { fprintf(stderr, "copy: BYTES must be a positive multiple of 16\n"); return 2; }
+  void *a, *b;
+  if (hipMalloc(&a, bytes) || hipMalloc(&b, bytes)) { fprintf(stderr, "device alloc\n"); return 1; }
+  hipMemset(a, 0, bytes);
+  hipEvent_t e0, e1;
+  hipEventCreate(&e0); hipEventCreate(&e1);
+  const size_t n = bytes / 16;
+  float best = 1e30f;
+  for (int r = 0; r < reps; r++) {
+    hipEventRecord(e0, nullptr);
+    hipLaunchKernelGGL(copy_kernel, dim3(4096), dim3(256), 0, nullptr, (const float4*)a, (float4*)b, n);
+    hipEventRecord(e1, nullptr);
+    hipEventSynchronize(e1);
+    float t;
+    hipEventElapsedTime(&t, e0, e1);
+    if (t < best) best = t;
+  }
+  printf("{\"copy_bytes\": %zu, \"reps\": %d, \"best_ms\": %.4f, \"gbs\": %.1f}\n", bytes, reps, best,
+         2.0 * bytes / (best * 1e-3) / 1e9);
+  hipFree(a); hipFree(b);
+  return 0;
+}
+
+int main(int argc, char** argv) {
+  if (argc > 1 && argv[1][0] == 'c')
+    return run_copy(argc > 2 ? strtoull(argv[2], nullptr, 10) : ((size_t)1 << 30), argc > 3 ? atoi(argv[3]) : 5);
+  const int64_t m = argc > 1 ? atoll(argv[1]) : 200000;
+  const int64_t n = argc > 2 ? atoll(argv[2]) : 4096;
+  const int k = argc > 3 ? atoi(argv[3]) : 64;
+  const double eps = argc > 4 ? atof(argv[4]) : 5e-8;
+  const int gram = argc > 5 ? atoi(argv[5]) : TSVD_GRAM_BF16X3;
+  const int steps = argc > 6 ? atoi(argv[6]) : 3;
+  const int warmup = argc > 7 ? atoi(argv[7]) : 1;
+  const uint64_t seed = argc > 8 ? strtoull(argv[8], nullptr, 10) : 7;
+  if (m < n || k > n) { fprintf(stderr, "need m >= n >= k\n"); return 2; }
+
+  // A = H_L [diag(s); 0] H_R, built row by row: row i of [diag(s); 0] H_R is
+  // s_i * (row i of H_R) for i < n and 0 otherwise; H_L mixes rows through two
+  // rank-1 corrections.
+  std::vector<double> wl[2], wr[2];
+  for (int r = 0; r < 2; r++) {
+    wl[r].resize(m); wr[r].resize(n);
+    double a = 0, b = 0;
+    for (int64_t i = 0; i < m; i++) { wl[r][i] = gauss(seed + 11 + r, i); a += wl[r][i] * wl[r][i]; }
+    for (int64_t j = 0; j < n; j++) { wr[r][j] = gauss(seed + 21 + r, j); b += wr[r][j] * wr[r][j]; }
+    a = 1.0 / sqrt(a); b = 1.0 / sqrt(b);
+    for (auto& x : wl[r]) x *= a;
+    for (auto& x : wr[r]) x *= b;
+  }
+  std::vector<double> s(n);
+  for (int64_t i = 0; i < n; i++) s[i] = pow(0.97, (double)i);
+  // D H_R rows: R_i = s_i e_i^T (I - 2 w1 w1^T)(I - 2 w2 w2^T)
+  // M0 = [D H_R; 0]; A = (I - 2 u1 u1^T)(I - 2 u2 u2^T) M0
+  // c_r = u_r^T M0 (n-vectors) are needed for the left reflectors.
+  auto row_dhr = [&](int64_t i, double* out) {  // i < n
+    for (int64_t j = 0; j < n; j++) out[j] = (j == i) ? s[i] : 0.0;
+    for (int r = 0; r < 2; r++) {
+      double dot = 0;
+      for (int64_t j = 0; j < n; j++) dot += out[j] * wr[r][j];
+      for (int64_t j = 0; j < n; j++) out[j] -= 2.0 * dot * wr[r][j];
+    }
+  };
+  std::vector<double> M0((size_t)n * n);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; i++) row_dhr(i, &M0[(size_t)i * n]);
+  // A = L2 L1 M0 with L_r = I - 2 u_r u_r^T applied as L2 (L1 M0):
+  // (L1 M0) = M0 - 2 u1 (u1^T M0); then L2 X = X - 2 u2 (u2^T X)
+  std::vector<double> c1(n, 0.0), c2(n, 0.0);
+  for (int64_t i = 0; i < n; i++)
+    for (int64_t j = 0; j < n; j++) c1[j] += wl[0][i] * M0[(size_t)i * n + j];
+  // u2^T (L1 M0) = u2^T M0 - 2 (u2.u1) c1
+  double u21 = 0;
+  for (int64_t i = 0; i < m; i++) u21 += wl[1][i] * wl[0][i];
+  for (int64_t i = 0; i < n; i++)
+    for (int64_t j = 0; j < n; j++) c2[j] += wl[1][i] * M0[(size_t)i * n + j];
+  for (int64_t j = 0; j < n; j++) c2[j] -= 2.0 * u21 * c1[j];
+  float* hA = nullptr;
+  if (hipHostMalloc((void**)&hA, (size_t)m * n * 4, hipHostMallocDefault) != hipSuccess) { fprintf(stderr, "host alloc\n"); return 1; }
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < m; i++) {
+    for (int64_t j = 0; j < n; j++) {
+      double x = i < n ? M0[(size_t)i * n + j] : 0.0;
+      x -= 2.0 * wl[0][i] * c1[j];
+      x -= 2.0 * wl[1][i] * c2[j];
+      hA[(size_t)i * n + j] = (float)x;
+    }
+  }
+  std::vector<double> hv0((size_t)k * n);
+  for (size_t i = 0; i < hv0.size(); i++) hv0[i] = gauss(seed + 31, i);
+
+  float* A; double *v0, *U, *S, *V;
+  if (hipMalloc(&A, (size_t)m * n * 4) || hipMalloc(&v0, hv0.size() * 8) || hipMalloc(&U, (size_t)m * k * 8) ||
+      hipMalloc(&S, (size_t)k * 8) || hipMalloc(&V, (size_t)n * k * 8)) { fprintf(stderr, "device alloc\n"); return 1; }
+  hipMemcpy(A, hA, (size_t)m * n * 4, hipMemcpyHostToDevice);
+  hipMemcpy(v0, hv0.data(), hv0.size() * 8, hipMemcpyHostToDevice);
+  tsvd_ctx* ctx;
+  if (tsvd_ctx_create(0, &ctx) != TSVD_OK) { fprintf(stderr, "ctx\n"); return 1; }
+  tsvd_opts o;
+  tsvd_opts_default(&o);
+  o.k = k; o.eps = eps; o.gram = gram; o.v0 = v0;
+  std::vector<int> iters(k);
+  tsvd_info info = {};
+  info.iters = iters.data();
+  for (int w = 0; w < warmup; w++) tsvd_dense(ctx, A, TSVD_F32, TSVD_LOC_DEVICE, m, n, n, &o, U, m, S, V, n, &info, nullptr);
+  hipDeviceSynchronize();
+  double tg = 0, te = 0, tf = 0;
+  const auto t0 = std::chrono::steady_clock::now();
+  tsvd_status st = TSVD_OK;
+  for (int i = 0; i < steps; i++) {
+    st = tsvd_dense(ctx, A, TSVD_F32, TSVD_LOC_DEVICE, m, n, n, &o, U, m, S, V, n, &info, nullptr);
+    tg += info.t_gram_ms; te += info.t_eig_ms; tf += info.t_final_ms;
+  }
+  hipDeviceSynchronize();
+  const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  std::vector<double> hS(k);
+  hipMemcpy(hS.data(), S, (size_t)k * 8, hipMemcpyDeviceToHost);
+  double err = 0;
+  for (int l = 0; l < k; l++) err = fmax(err, fabs(hS[l] - s[l]) / s[l]);
+  long it_total = 0;
+  for (int l = 0; l < k; l++) it_total += iters[l];
+  printf("{\"status\": \"%s\", \"m\": %lld, \"n\": %lld, \"k\": %d, \"eps\": %g, \"gram\": %d, \"steps\": %d, "
+         "\"ms_per_step\": %.3f, \"triplets_per_s\": %.2f, \"gram_ms\": %.3f, \"power_ms\": %.3f, \"finish_ms\": %.3f, "
+         "\"iters_total\": %ld, \"sigma_rel_err_max\": %.3e}\n",
+         tsvd_status_string(st), (long long)m, (long long)n, k, eps, gram, steps, dt * 1e3 / steps, k * steps / dt,
+         tg / steps, te / steps, tf / steps, it_total, err);
+  fflush(stdout);
+  tsvd_ctx_destroy(ctx);
+  hipFree(A); hipFree(v0); hipFree(U); hipFree(S); hipFree(V);
+  hipHostFree(hA);
+  return st == TSVD_OK ? 0 : 1;
+}

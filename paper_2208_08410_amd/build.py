@@ -21,6 +21,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libtsvd.so")
+DRIVER_SRC = os.path.join(PKG, "bench_driver.cpp")
+DRIVER = os.path.join(PKG, "tsvd_bench")
 
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -68,6 +70,15 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout + r.stderr)
     shutil.move(tmp, LIB)
+    # stand-alone profiling driver linked against the library
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-O2", "-std=c++17", "-fopenmp", DRIVER_SRC, "-o", DRIVER + ".tmp",
+           "-L" + PKG, "-ltsvd", "-Wl,-rpath,$ORIGIN"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("driver build failed:\n" + r.stdout + r.stderr)
+    shutil.move(DRIVER + ".tmp", DRIVER)
     return LIB
 
 

@@ -20,14 +20,14 @@ __device__ __forceinline__ int kpos4(int k) { return (k & 3) * 4 + (k >> 2); }
 // W[M x N] (column-major, ldw) = op(A) X, X is K x N column-major (ldx).
 // side 0: op(A) = A (M = m, K = n); side 1: op(A) = A^T (M = n, K = m).
 template <typename AT, int SIDE>
-__global__ __launch_bounds__(256) void finish_gemm_kernel(const AT* A, int64_t lda, int64_t M, int64_t K,
-                                                          const double* X, int64_t ldx, int N, double* W,
-                                                          int64_t ldw, double* ssq) {
+__device__ __forceinline__ void finish_gemm_unit(const AT* A, int64_t lda, int64_t M, int64_t K, const double* X,
+                                                 int64_t ldx, int N, double* W, int64_t ldw, double* ssq, int bx,
+                                                 int by) {
   __shared__ double As[2][FBM * FLDK];
   __shared__ double Xs[2][FBN * FLDK];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t m0 = (int64_t)blockIdx.x * FBM;
-  const int j0 = blockIdx.y * FBN;
+  const int64_t m0 = (int64_t)bx * FBM;
+  const int j0 = by * FBN;
   const int nk = (int)((K + FBK - 1) / FBK);
 
   double av[8], xv[4];
@@ -125,8 +125,15 @@ __global__ __launch_bounds__(256) void finish_gemm_kernel(const AT* A, int64_t l
   __syncthreads();
   if (tid < FBN && j0 + tid < N) {
     const double t = colss[0][tid] + colss[1][tid] + colss[2][tid] + colss[3][tid];
-    ssq[(int64_t)blockIdx.x * N + j0 + tid] = t;
+    ssq[(int64_t)bx * N + j0 + tid] = t;
   }
+}
+
+template <typename AT, int SIDE>
+__global__ __launch_bounds__(256) void finish_gemm_kernel(const AT* A, int64_t lda, int64_t M, int64_t K,
+                                                          const double* X, int64_t ldx, int N, double* W,
+                                                          int64_t ldw, double* ssq) {
+  finish_gemm_unit<AT, SIDE>(A, lda, M, K, X, ldx, N, W, ldw, ssq, blockIdx.x, blockIdx.y);
 }
 
 // sigma_j = sqrt(sum over row tiles of ssq[b][j]), added in tile order.
@@ -141,10 +148,9 @@ __global__ void finish_sigma_kernel(const double* ssq, int nb, int N, double* S)
 // Column j: divide W[:, j] by S[j] (zero columns stay zero), then find the
 // largest-|.| entry of V[:, j] (ties: lowest index) and flip V[:, j] and
 // U[:, j] if it is negative.  W aliases U (side RIGHT) or V (side LEFT).
-__global__ __launch_bounds__(256) void finish_scale_sign_kernel(double* W, int64_t ldw, int64_t Mw, const double* S,
-                                                                double* V, int64_t ldv, int64_t n, double* U,
-                                                                int64_t ldu, int64_t m, int do_sign) {
-  const int j = blockIdx.x;
+__device__ __forceinline__ void scale_sign_column(double* W, int64_t ldw, int64_t Mw, const double* S, double* V,
+                                                  int64_t ldv, int64_t n, double* U, int64_t ldu, int64_t m,
+                                                  int do_sign, int j) {
   const int tid = threadIdx.x;
   const double s = S[j];
   const double inv = s > 0.0 ? 1.0 / s : 0.0;
@@ -181,14 +187,80 @@ __global__ __launch_bounds__(256) void finish_scale_sign_kernel(double* W, int64
   }
 }
 
+__global__ __launch_bounds__(256) void finish_scale_sign_kernel(double* W, int64_t ldw, int64_t Mw, const double* S,
+                                                                double* V, int64_t ldv, int64_t n, double* U,
+                                                                int64_t ldu, int64_t m, int do_sign) {
+  scale_sign_column(W, ldw, Mw, S, V, ldv, n, U, ldu, m, do_sign, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Grouped finishing pass for a batch (FP32 A): one launch for the products of
+// every problem (units = row tiles x column blocks), one for sigma (a block per
+// problem), one for scale and signs (a block per column of each problem).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int find_fjob(const FinishJob* jobs, int njobs, int64_t u, int which) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    const int64_t b = which == 0 ? jobs[mid].ubegin : jobs[mid].cbegin;
+    if (b <= u) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <int SIDE>
+__global__ __launch_bounds__(256) void finish_grouped_gemm_kernel(const FinishJob* jobs, int njobs) {
+  const int jb = find_fjob(jobs, njobs, blockIdx.x, 0);
+  const FinishJob& j = jobs[jb];
+  const int u = (int)(blockIdx.x - j.ubegin);
+  const int64_t M = SIDE == 0 ? j.m : j.n, K = SIDE == 0 ? j.n : j.m;
+  const double* X = SIDE == 0 ? j.V : j.U;
+  const int64_t ldx = SIDE == 0 ? j.ldv : j.ldu;
+  double* W = SIDE == 0 ? j.U : j.V;
+  const int64_t ldw = SIDE == 0 ? j.ldu : j.ldv;
+  finish_gemm_unit<float, SIDE>((const float*)j.A, j.lda, M, K, X, ldx, j.k, W, ldw, j.ssq, u % j.nb, u / j.nb);
+}
+
+__global__ void finish_grouped_sigma_kernel(const FinishJob* jobs) {
+  const FinishJob& j = jobs[blockIdx.x];
+  for (int c = threadIdx.x; c < j.k; c += blockDim.x) {
+    double t = 0.0;
+    for (int b = 0; b < j.nb; b++) t += j.ssq[(int64_t)b * j.k + c];
+    j.S[c] = sqrt(t);
+  }
+}
+
+__global__ __launch_bounds__(256) void finish_grouped_scale_kernel(const FinishJob* jobs, int njobs) {
+  const int jb = find_fjob(jobs, njobs, blockIdx.x, 1);
+  const FinishJob& j = jobs[jb];
+  const int c = (int)(blockIdx.x - j.cbegin);
+  double* W = j.side == 0 ? j.U : j.V;
+  const int64_t ldw = j.side == 0 ? j.ldu : j.ldv;
+  const int64_t Mw = j.side == 0 ? j.m : j.n;
+  scale_sign_column(W, ldw, Mw, j.S, j.V, j.ldv, j.n, j.U, j.ldu, j.m, 1, c);
+}
+
+int finish_grouped_launch(int side, const FinishJob* d_jobs, int njobs, int64_t units, int64_t cols, hipStream_t s) {
+  if (njobs <= 0) return 0;
+  if (side == 0) hipLaunchKernelGGL(finish_grouped_gemm_kernel<0>, dim3((unsigned)units), dim3(256), 0, s, d_jobs, njobs);
+  else hipLaunchKernelGGL(finish_grouped_gemm_kernel<1>, dim3((unsigned)units), dim3(256), 0, s, d_jobs, njobs);
+  TSVD_HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(finish_grouped_sigma_kernel, dim3(njobs), dim3(64), 0, s, d_jobs);
+  TSVD_HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(finish_grouped_scale_kernel, dim3((unsigned)cols), dim3(256), 0, s, d_jobs, njobs);
+  TSVD_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
 int finish_workspace_doubles(int64_t m, int64_t n, int side, int k) {
   const int64_t M = side == 0 ? m : n;
   const int64_t nb = (M + FBM - 1) / FBM;
   return (int)(nb * k);
 }
 
-int finish_launch(int is_f64, int side, const void* A, int64_t m, int64_t n, int64_t lda, const double* X,
-                  int64_t ldx, int k, double* W, int64_t ldw, double* S, double* ssq, hipStream_t stream) {
+int finish_gemm_launch(int is_f64, int side, const void* A, int64_t m, int64_t n, int64_t lda, const double* X,
+                       int64_t ldx, int k, double* W, int64_t ldw, double* ssq, hipStream_t stream) {
   const int64_t M = side == 0 ? m : n;
   const int64_t K = side == 0 ? n : m;
   const int64_t nb = (M + FBM - 1) / FBM;
@@ -209,9 +281,21 @@ int finish_launch(int is_f64, int side, const void* A, int64_t m, int64_t n, int
                          ldx, k, W, ldw, ssq);
   }
   TSVD_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int finish_sigma_launch(const double* ssq, int64_t nb, int k, double* S, hipStream_t stream) {
   hipLaunchKernelGGL(finish_sigma_kernel, dim3((k + 127) / 128), dim3(128), 0, stream, ssq, (int)nb, k, S);
   TSVD_HIP_TRY(hipGetLastError());
   return 0;
+}
+
+int finish_launch(int is_f64, int side, const void* A, int64_t m, int64_t n, int64_t lda, const double* X,
+                  int64_t ldx, int k, double* W, int64_t ldw, double* S, double* ssq, hipStream_t stream) {
+  int rc = finish_gemm_launch(is_f64, side, A, m, n, lda, X, ldx, k, W, ldw, ssq, stream);
+  if (rc) return rc;
+  const int64_t M = side == 0 ? m : n;
+  return finish_sigma_launch(ssq, (M + FBM - 1) / FBM, k, S, stream);
 }
 
 int finish_scale_sign_launch(double* W, int64_t ldw, int64_t Mw, const double* S, double* V, int64_t ldv, int64_t n,

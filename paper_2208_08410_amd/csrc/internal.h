@@ -15,9 +15,28 @@ struct SyrkPlan {
   int64_t kchunk, partial_elems;
   size_t partial_bytes;
 };
-int syrk_plan(int mode, int64_t d, int64_t K, int64_t rows_per_block, int num_cu, SyrkPlan* p);
+int syrk_plan(int mode, int64_t d, int64_t K, int64_t rows_per_block, int num_cu, SyrkPlan* p, int tile = 0,
+              int chunks = 0);
 int syrk_launch(int mode, int side, const void* A, int64_t m, int64_t n, int64_t lda, const SyrkPlan& p,
                 void* partial, void* B, int64_t ldb, int accumulate, hipStream_t stream);
+
+// one problem of a grouped (batched) Gram launch; 128-wide tiles
+struct GramJob {
+  const void* A;
+  int64_t m, n, lda;
+  int side;              // 0: A^T A, 1: A A^T
+  int nt, T, S;
+  int64_t kchunk;
+  int vec_ok;
+  int pad;
+  void* partial;         // S * T * 128 * 128 floats
+  void* B;               // d x d (ldb)
+  int64_t ldb;
+  int64_t ubegin;        // first workgroup of this job in the partial launch
+  int64_t rbegin;        // first workgroup of this job in the reduce launch
+};
+int syrk_grouped_launch(int mode, int side, const GramJob* d_jobs, int njobs, int64_t units, int64_t runits,
+                        hipStream_t s);
 
 // ---- power iteration (power.hip)
 struct PowerArgs {
@@ -42,6 +61,21 @@ struct PowerArgs {
   int vec_ok;               // 16-byte loads allowed on B rows
   int64_t spin_limit;
   double* kscr;             // device, G * 2 * (k + 2) doubles (per-block scratch)
+  int64_t xwords;           // words per parity of xex
+  int64_t vstride;          // words per parity of vex / wex
+};
+// A team of the batched power launch: workgroups [first, first + size) solve
+// problems order[pbegin..pend) with their own exchange buffers.
+struct PowerTeam {
+  int first, size, pbegin, pend;
+  uint64_t* xex;
+  uint64_t* pex;
+  uint64_t* vex;
+  uint64_t* wex;
+  double* kscr;
+  int pw;
+  int pad;
+  int64_t xwords, vstride;
 };
 struct PowerPlan {
   int G, rpb, cache_rows, ldsB, pw;
@@ -53,10 +87,48 @@ int power_plan(int dtype_bytes, int d, int k, int num_cu, size_t max_lds, int ma
 int power_launch(int is_f64, const PowerPlan& p, PowerArgs a, hipStream_t stream);
 
 // ---- finishing pass (finish.hip)
+// one problem of a grouped finishing pass (FP32 A); k = triplets found
+struct FinishJob {
+  const void* A;
+  int64_t m, n, lda;
+  int side, k;
+  double* U;
+  int64_t ldu;
+  double* V;
+  int64_t ldv;
+  double* S;
+  double* ssq;           // nb * k
+  int nb, pad;           // row tiles of the product
+  int64_t ubegin;        // first workgroup in the product launch (nb * column blocks units)
+  int64_t cbegin;        // first workgroup in the scale launch (k units)
+};
+int finish_grouped_launch(int side, const FinishJob* d_jobs, int njobs, int64_t units, int64_t cols, hipStream_t s);
 int finish_workspace_doubles(int64_t m, int64_t n, int side, int k);
+int finish_gemm_launch(int is_f64, int side, const void* A, int64_t m, int64_t n, int64_t lda, const double* X,
+                       int64_t ldx, int k, double* W, int64_t ldw, double* ssq, hipStream_t stream);
+int finish_sigma_launch(const double* ssq, int64_t nb, int k, double* S, hipStream_t stream);
 int finish_launch(int is_f64, int side, const void* A, int64_t m, int64_t n, int64_t lda, const double* X,
                   int64_t ldx, int k, double* W, int64_t ldw, double* S, double* ssq, hipStream_t stream);
 int finish_scale_sign_launch(double* W, int64_t ldw, int64_t Mw, const double* S, double* V, int64_t ldv, int64_t n,
                              double* U, int64_t ldu, int64_t m, int k, int do_sign, hipStream_t stream);
+
+// ---- sparse path (sparse.hip)
+int csr_validate(const int64_t* rowptr, const int32_t* col, int64_t m, int64_t n, int64_t nnz, int* d_bad,
+                 hipStream_t s);
+size_t csc_build_scratch_bytes(int64_t n);
+int csc_build(const int64_t* rowptr, const int32_t* col, const float* val, int64_t m, int64_t n, int64_t nnz,
+              int64_t* colptr, int32_t* rowidx, float* cval, void* scratch, hipStream_t s);
+int spmv_launch(const int64_t* ptr, const int32_t* idx, const float* val, const void* x, int x_is_f64, int64_t rows,
+                int64_t nnz, double* y, float* yf, hipStream_t s);
+int64_t proj_blocks(int64_t d);
+int proj_partials_launch(const double* V, int64_t ldv, int l, const double* w, const double* x, int64_t d,
+                         double* partial, double* out, hipStream_t s);
+int proj_apply_launch(const double* V, int64_t ldv, int l, const double* coef, double* w, int64_t d, double* partial,
+                      double* out, hipStream_t s);
+int sumsq_launch(const double* v, int64_t d, double* partial, double* out, hipStream_t s);
+int normalize_launch(const double* z, int64_t d, double inv, double* x, float* xf, hipStream_t s);
+int start_scale_launch(const double* v0, int64_t d, const double* ss, double* x, hipStream_t s);
+int to_float_launch(const double* x, int64_t d, float* xf, hipStream_t s);
+int sqrt_inplace_launch(double* v, int n, hipStream_t s);
 
 }  // namespace tsvd

@@ -50,23 +50,26 @@ __device__ __forceinline__ void load_vec<double>(const double* p, double (&v)[2]
 }
 
 // y[li] = B row li . x for rows li in [begin, end) of one storage (LDS or HBM).
-// Wave w takes rows begin + 16 g + 4 w + q, q < 4, processing 4 rows per pass so
-// each x chunk read from LDS feeds 4 rows.
+// Rows are dealt to the 4 waves round-robin (wave w: begin + w + 4j); a wave
+// takes 4 of its rows per pass so each x chunk read from LDS feeds 4 rows.
 template <typename BT>
 __device__ void gemv_range(const BT* rows, int64_t stride, int begin, int end, const BT* xs, int d, bool vec_ok,
                            double* yout) {
   constexpr int VN = VecOf<BT>::N;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int dv = vec_ok ? (d / VN) * VN : 0;
-  for (int g0 = begin; g0 < end; g0 += 16) {
-    const int li0 = g0 + wave * 4;
-    if (li0 >= end) continue;
-    const int nr = min(4, end - li0);
+  for (int j0 = 0; begin + wave + 4 * j0 < end; j0 += 4) {
+    int li[4];
+    int nr = 0;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      li[q] = begin + wave + 4 * (j0 + q);
+      if (li[q] < end) nr = q + 1;
+    }
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     const BT* rp[4];
 #pragma unroll
-    for (int q = 0; q < 4; q++) rp[q] = rows + (int64_t)(li0 + (q < nr ? q : 0)) * stride;
-#pragma unroll 2
+    for (int q = 0; q < 4; q++) rp[q] = rows + (int64_t)(q < nr ? li[q] : li[0]) * stride;
     for (int c = lane * VN; c < dv; c += 64 * VN) {
       double xv[VN];
       load_vec<BT>(xs + c, xv);
@@ -89,25 +92,60 @@ __device__ void gemv_range(const BT* rows, int64_t stride, int begin, int end, c
 #pragma unroll
     for (int q = 0; q < 4; q++) {
       double s = wave_sum(acc[q]);
-      if (lane == 0 && q < nr) yout[li0 + q] = s;
+      if (lane == 0 && q < nr) yout[li[q]] = s;
     }
   }
 }
 
-template <typename BT>
-__device__ __forceinline__ void gemv_own(const PowerArgs& a, const BT* Bs, const BT* Bg, int nrows, const BT* xs,
-                                         double* yout) {
-  const int cr = min(a.cache_rows, nrows);
-  gemv_range<BT>(Bs, a.ldsB, 0, cr, xs, a.d, true, yout);
-  gemv_range<BT>(Bg + (int64_t)cr * a.ldb, a.ldb, 0, nrows - cr, xs, a.d, a.vec_ok != 0, yout + cr);
+// Register-resident rows: wave w holds rows cr + w + 4q (q < RR) of its block,
+// lane l keeping columns VN*l + 64*VN*s + e (s < NV, e < VN), zero beyond d.
+template <typename BT, int NV, int RR>
+struct RegRows {
+  static constexpr int VN = VecOf<BT>::N;
+  BT v[RR > 0 ? RR : 1][NV > 0 ? NV : 1][VN];
+};
+
+template <typename BT, int NV, int RR>
+__device__ __forceinline__ void gemv_regrows(const RegRows<BT, NV, RR>& R, int cr, int nreg, const BT* xs,
+                                             double* yout) {
+  if constexpr (RR > 0 && NV > 0) {
+    // per-lane partial sums in BT (64 products per row per lane at d = 4096),
+    // summed across lanes in FP64
+    constexpr int VN = VecOf<BT>::N;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    BT acc[RR];
+#pragma unroll
+    for (int q = 0; q < RR; q++) acc[q] = (BT)0;
+#pragma unroll
+    for (int s = 0; s < NV; s++) {
+      BT xv[VN];
+      if constexpr (VN == 4) {
+        const float4 f = *(const float4*)(xs + VN * lane + 64 * VN * s);
+        xv[0] = f.x; xv[1] = f.y; xv[2] = f.z; xv[3] = f.w;
+      } else {
+        const double2 f = *(const double2*)(xs + VN * lane + 64 * VN * s);
+        xv[0] = f.x; xv[1] = f.y;
+      }
+#pragma unroll
+      for (int q = 0; q < RR; q++)
+#pragma unroll
+        for (int e = 0; e < VN; e++) acc[q] = fma(R.v[q][s][e], xv[e], acc[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < RR; q++) {
+      const int li = wave + 4 * q;
+      double sum = wave_sum((double)acc[q]);
+      if (lane == 0 && li < nreg) yout[cr + li] = sum;
+    }
+  }
 }
 
 // Sum vals[0..P) over all G workgroups (published in the partial buffer under
 // epoch ex); out[0..P) receives the totals, identical in every workgroup.
 // Returns false (uniformly in the block) if a wait ran out of budget.
-__device__ bool allreduce_blocks(uint64_t* pbuf, int pw, int G, uint32_t ex, const double* vals, int P, double* out,
-                                 double* scratch, int* flag, int64_t spin_limit) {
-  const int tid = threadIdx.x, b = blockIdx.x;
+__device__ bool allreduce_blocks(uint64_t* pbuf, int pw, int b, int G, uint32_t ex, const double* vals, int P,
+                                 double* out, double* scratch, int* flag, int64_t spin_limit) {
+  const int tid = threadIdx.x;
   for (int j = tid; j < P; j += 256) ll_store_f64(pbuf + (int64_t)b * pw + 2 * j, ex, vals[j]);
   if (tid == 0) *flag = 1;
   __syncthreads();
@@ -172,42 +210,6 @@ __device__ bool allreduce_blocks(uint64_t* pbuf, int pw, int G, uint32_t ex, con
   return res;
 }
 
-// Publish own rows of a vector (FP64 values in `own`, rows r0..r0+nrows) as
-// words of type BT (1 word per float, 2 per double).
-template <typename BT>
-__device__ __forceinline__ void publish_vec(uint64_t* buf, uint32_t ex, int r0, int nrows, const double* own,
-                                            double scale) {
-  for (int i = threadIdx.x; i < nrows; i += 256) {
-    const double v = own[i] * scale;
-    if constexpr (sizeof(BT) == 4) {
-      ll_store(buf + (r0 + i), ex, __float_as_uint((float)v));
-    } else {
-      ll_store_f64(buf + 2 * (int64_t)(r0 + i), ex, v);
-    }
-  }
-}
-
-// Gather a published BT vector of length d into LDS dst (as BT), multiplying by
-// scale.  Returns false (block-uniform) on a timed-out wait.
-template <typename BT>
-__device__ bool gather_vec(const uint64_t* buf, uint32_t ex, int d, BT* dst, double scale, int* flag,
-                           int64_t spin_limit) {
-  constexpr int WPE = sizeof(BT) / 4;
-  if (threadIdx.x == 0) *flag = 1;
-  __syncthreads();
-  int64_t budget = spin_limit;
-  uint32_t* raw = (uint32_t*)dst;
-  bool ok = ll_read_words<16>(buf, (int64_t)d * WPE, ex, threadIdx.x, 256, budget,
-                              [&](int64_t idx, uint32_t payload) { raw[idx] = payload; });
-  if (!ok) *flag = 0;
-  __syncthreads();
-  const bool res = *flag != 0;
-  if (res && scale != 1.0)
-    for (int c = threadIdx.x; c < d; c += 256) dst[c] = (BT)((double)dst[c] * scale);
-  __syncthreads();
-  return res;
-}
-
 // Gather a published FP64 vector (2 words per element) into dst as BT.
 template <typename BT>
 __device__ bool gather_f64_as(const uint64_t* buf, uint32_t ex, int d, BT* dst, int* flag, int64_t spin_limit) {
@@ -255,11 +257,142 @@ __device__ bool gather_f64_as(const uint64_t* buf, uint32_t ex, int d, BT* dst, 
   return res;
 }
 
+// Iteration exchange: wait until every y word of this epoch (rotated start per
+// block to spread the requests over memory channels) and every block's two
+// partials are published; y lands in xs (raw), partials are summed with a
+// fixed-shape tree.  Returns false (block-uniform) on a timed-out wait.
 template <typename BT>
-__global__ __launch_bounds__(256) void power_kernel(PowerArgs a) {
-  extern __shared__ __align__(16) unsigned char smem[];
+__device__ bool gather_iteration(const uint64_t* xb, const uint64_t* pb, uint32_t ex, int d, int b, int G, BT* xs,
+                                 double* red, int* flag, int64_t spin_limit, double& q, double& dd) {
+  constexpr int WPE = sizeof(BT) / 4;
+  constexpr int W = 8;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int G = gridDim.x, b = blockIdx.x;
+  const int count = d * WPE;
+  const int rot = (int)(((int64_t)b * 1031) % count);
+  uint32_t* raw = (uint32_t*)xs;
+  int64_t budget = spin_limit;
+  bool ok = true;
+  double pq = 0.0, pd = 0.0;
+  for (int base = 0; base < count && ok; base += 256 * W) {
+    uint64_t w[W];
+    uint64_t pw4[4];
+    const bool first = base == 0;
+#pragma unroll
+    for (int j = 0; j < W; j++) {
+      const int i = base + tid + 256 * j;
+      int ii = i + rot;
+      if (ii >= count) ii -= count;
+      w[j] = i < count ? ll_load(xb + ii) : ((uint64_t)ex << 32);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; j++) pw4[j] = (first && tid < G) ? ll_load(pb + 4 * (int64_t)tid + j) : ((uint64_t)ex << 32);
+    while (true) {
+      bool all = true;
+#pragma unroll
+      for (int j = 0; j < W; j++) all = all && ((uint32_t)(w[j] >> 32) == ex);
+#pragma unroll
+      for (int j = 0; j < 4; j++) all = all && ((uint32_t)(pw4[j] >> 32) == ex);
+      if (all) break;
+      if (--budget <= 0) { ok = false; break; }
+      __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+      for (int j = 0; j < W; j++) {
+        const int i = base + tid + 256 * j;
+        int ii = i + rot;
+        if (ii >= count) ii -= count;
+        if (i < count && (uint32_t)(w[j] >> 32) != ex) w[j] = ll_load(xb + ii);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; j++)
+        if (first && tid < G && (uint32_t)(pw4[j] >> 32) != ex) pw4[j] = ll_load(pb + 4 * (int64_t)tid + j);
+    }
+    if (ok) {
+#pragma unroll
+      for (int j = 0; j < W; j++) {
+        const int i = base + tid + 256 * j;
+        int ii = i + rot;
+        if (ii >= count) ii -= count;
+        if (i < count) raw[ii] = (uint32_t)w[j];
+      }
+      if (first && tid < G) { pq = ll_join_f64(pw4[0], pw4[1]); pd = ll_join_f64(pw4[2], pw4[3]); }
+    }
+  }
+  if (tid == 0) *flag = 1;
+  __syncthreads();
+  if (!ok) *flag = 0;
+  pq = wave_sum(pq);
+  pd = wave_sum(pd);
+  if (lane == 0) { red[wave] = pq; red[4 + wave] = pd; }
+  __syncthreads();
+  q = (red[0] + red[1]) + (red[2] + red[3]);
+  dd = (red[4] + red[5]) + (red[6] + red[7]);
+  const bool res = *flag != 0;
+  __syncthreads();
+  return res;
+}
+
+// B[li][c] -= coef[li] * z[c] for every own row li (LDS rows [0, cr), the
+// rest in B) and column c < d; z is a vector in LDS.
+template <typename BT>
+__device__ void deflate_rows(const PowerArgs& a, BT* Bs, BT* Bg, int cr, int nrows, const BT* z, const double* coef) {
+  const int tid = threadIdx.x;
+  const int d = a.d;
+  for (int li = 0; li < nrows; li++) {
+    BT* row = li < cr ? Bs + (int64_t)li * a.ldsB : Bg + (int64_t)li * a.ldb;
+    const double ci = coef[li];
+    for (int c = tid; c < d; c += 256) row[c] = (BT)fma(-ci, (double)z[c], (double)row[c]);
+  }
+}
+
+template <typename BT, int NV, int RR>
+__device__ __forceinline__ void load_regrows(RegRows<BT, NV, RR>& R, const BT* Bg, int64_t ldb, int cr, int nreg,
+                                             int d) {
+  if constexpr (RR > 0 && NV > 0) {
+    constexpr int VN = VecOf<BT>::N;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < RR; q++) {
+      const bool live = wave + 4 * q < nreg;
+      const BT* row = Bg + (int64_t)(cr + wave + 4 * q) * ldb;
+#pragma unroll
+      for (int s = 0; s < NV; s++)
+#pragma unroll
+        for (int e = 0; e < VN; e++) {
+          const int c = VN * lane + 64 * VN * s + e;
+          R.v[q][s][e] = (live && c < d) ? row[c] : (BT)0;
+        }
+    }
+  }
+}
+
+template <typename BT, int NV, int RR>
+__device__ __forceinline__ void store_regrows(const RegRows<BT, NV, RR>& R, BT* Bg, int64_t ldb, int cr, int nreg,
+                                              int d) {
+  if constexpr (RR > 0 && NV > 0) {
+    constexpr int VN = VecOf<BT>::N;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < RR; q++) {
+      const bool live = wave + 4 * q < nreg;
+      BT* row = Bg + (int64_t)(cr + wave + 4 * q) * ldb;
+#pragma unroll
+      for (int s = 0; s < NV; s++)
+#pragma unroll
+        for (int e = 0; e < VN; e++) {
+          const int c = VN * lane + 64 * VN * s + e;
+          if (live && c < d) row[c] = R.v[q][s][e];
+        }
+    }
+  }
+}
+
+// One problem solved by a team of G workgroups (this one is member b).  The
+// exchange counters persist across problems solved by the same team.
+template <typename BT, int NV, int RR>
+__device__ void solve_problem(const PowerArgs& a, int b, int G, unsigned char* smem, uint32_t& epoch, uint32_t& nx,
+                              uint32_t& np) {
+  constexpr int VN = VecOf<BT>::N;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int d = a.d;
   const int dpad = (d + 3) & ~3;
   const int r0 = b * a.rpb;
@@ -272,26 +405,28 @@ __global__ __launch_bounds__(256) void power_kernel(PowerArgs a) {
   double* vv = xv + rpbA;               // own rows: v (FP64) at the end of a triplet
   double* wv = vv + rpbA;               // own rows: w = B v
   double* scratch = wv + rpbA;          // 256: allreduce scratch
-  double* redw = scratch + 256;         // 8: block_sum scratch
+  double* redw = scratch + 256;         // 8: block_sum / tree scratch
   double* sv = redw + 8;                // 8: small values to publish
   double* st = sv + 8;                  // 16: small totals
   int* flag = (int*)(st + 16);          // block-uniform ok flag (2 doubles reserved)
-  BT* xs = (BT*)(st + 18);              // dpad: iterate (GEMV input)
-  BT* aux = xs + dpad;                  // dpad: w during deflation
-  BT* Bs = aux + dpad;                  // cache_rows x ldsB
+  BT* xs = (BT*)(st + 18);              // dpad: iterate (GEMV input), zero padded
+  BT* Bs = xs + dpad;                   // cache_rows x ldsB
   BT* Bg = (BT*)a.B + (int64_t)r0 * a.ldb;
   double* kvals = a.kscr + (int64_t)b * 2 * (a.k + 2);  // per-block global scratch
   double* ktot = kvals + (a.k + 2);
 
-  // one-time load of the cached rows
+  // row classes: [0, cr) in LDS, [cr, cr + nreg) in registers, the rest read from B
   const int cr = min(a.cache_rows, nrows);
+  const int nreg = (RR > 0 && NV > 0) ? min(4 * RR, nrows - cr) : 0;
+  const int g0 = cr + nreg;
+
+  // one-time loads
   for (int li = 0; li < a.cache_rows; li++)
     for (int c = tid; c < a.ldsB; c += 256)
       Bs[li * a.ldsB + c] = (li < cr && c < d) ? Bg[(int64_t)li * a.ldb + c] : (BT)0;
   __syncthreads();
 
-  uint32_t epoch = 0, nx = 0, np = 0;
-  const int64_t xwords = (int64_t)dpad * (sizeof(BT) / 4);
+  const int64_t xwords = a.xwords;
   int err = ERR_NONE;
   int kdone = a.k;
   bool all_conv = true, rankdef = false;
@@ -305,7 +440,7 @@ __global__ __launch_bounds__(256) void power_kernel(PowerArgs a) {
     if (!isfinite(ss)) { err = ERR_NONFINITE; break; }
     if (!(ss > 0.0)) { err = ERR_BADSTART; break; }
     const double inv0 = 1.0 / sqrt(ss);
-    for (int c = tid; c < dpad; c += 256) { xs[c] = c < d ? (BT)(v0[c] * inv0) : (BT)0; aux[c] = (BT)0; }
+    for (int c = tid; c < dpad; c += 256) xs[c] = c < d ? (BT)(v0[c] * inv0) : (BT)0;
     for (int i = tid; i < nrows; i += 256) xv[i] = v0[r0 + i] * inv0;
     __syncthreads();
 
@@ -313,22 +448,35 @@ __global__ __launch_bounds__(256) void power_kernel(PowerArgs a) {
     int it = 0;
     double nrm = 0.0;
     bool conv = false;
+    // register rows live only for this triplet's iterations: loaded from B here,
+    // written back before the deflation (which updates them in B)
+    RegRows<BT, NV, RR> R;
+    load_regrows<BT, NV, RR>(R, Bg, a.ldb, cr, nreg, d);
     while (true) {
-      gemv_own<BT>(a, Bs, Bg, nrows, xs, yv);
+      // ---- y = B x on the block's rows
+      gemv_regrows<BT, NV, RR>(R, cr, nreg, xs, yv);
+      gemv_range<BT>(Bs, a.ldsB, 0, cr, xs, d, true, yv);
+      gemv_range<BT>(Bg, a.ldb, g0, nrows, xs, d, a.vec_ok != 0, yv);
       __syncthreads();
       it++;
-      if (tid == 0) {
-        double q = 0.0, dd = 0.0;
-        for (int i = 0; i < nrows; i++) { q = fma(yv[i], yv[i], q); dd = fma(xv[i], yv[i], dd); }
-        sv[0] = q; sv[1] = dd;
-      }
-      __syncthreads();
+      // ---- publish y (own rows) and the block partials ||y_R||^2, x_R . y_R
       ++epoch;
       uint64_t* xb = a.xex + (int64_t)(nx & 1) * xwords; nx++;
       uint64_t* pb = a.pex + (int64_t)(np & 1) * G * a.pw; np++;
-      publish_vec<BT>(xb, epoch, r0, nrows, yv, 1.0);
-      if (!allreduce_blocks(pb, a.pw, G, epoch, sv, 2, st, scratch, flag, a.spin_limit)) { err = ERR_SPIN; break; }
-      const double q = st[0], dd = st[1];
+      if (wave == 0) {
+        double q = 0.0, dd = 0.0;
+        for (int i = lane; i < nrows; i += 64) { q = fma(yv[i], yv[i], q); dd = fma(xv[i], yv[i], dd); }
+        q = wave_sum(q);
+        dd = wave_sum(dd);
+        if (lane == 0) { ll_store_f64(pb + 4 * (int64_t)b, epoch, q); ll_store_f64(pb + 4 * (int64_t)b + 2, epoch, dd); }
+      }
+      for (int i = tid; i < nrows; i += 256) {
+        if constexpr (sizeof(BT) == 4) ll_store(xb + (r0 + i), epoch, __float_as_uint((float)yv[i]));
+        else ll_store_f64(xb + 2 * (int64_t)(r0 + i), epoch, yv[i]);
+      }
+      // ---- one wait for every block's y and partials
+      double q, dd;
+      if (!gather_iteration<BT>(xb, pb, epoch, d, b, G, xs, redw, flag, a.spin_limit, q, dd)) { err = ERR_SPIN; break; }
       nrm = sqrt(q);
       if (!isfinite(nrm)) { err = ERR_NONFINITE; break; }
       if (nrm == 0.0) { rankdef = true; kdone = l; break; }
@@ -344,12 +492,28 @@ __global__ __launch_bounds__(256) void power_kernel(PowerArgs a) {
         __syncthreads();
         break;
       }
-      if (!gather_vec<BT>(xb, epoch, d, xs, inv, flag, a.spin_limit)) { err = ERR_SPIN; break; }
+      // x = y / ||y|| (each thread scales the entries it gathered: same index set)
+      {
+        const int count = d * (int)(sizeof(BT) / 4);
+        const int rot = (int)(((int64_t)b * 1031) % count);
+        if constexpr (sizeof(BT) == 4) {
+          for (int i = tid; i < count; i += 256) {
+            int ii = i + rot;
+            if (ii >= count) ii -= count;
+            xs[ii] = (BT)((double)xs[ii] * inv);
+          }
+        }
+      }
+      __syncthreads();
+      if constexpr (sizeof(BT) == 8) {
+        for (int c = tid; c < d; c += 256) xs[c] = xs[c] * inv;
+      }
       for (int i = tid; i < nrows; i += 256) xv[i] = yv[i] * inv;
       __syncthreads();
     }
     if (err != ERR_NONE || rankdef) break;
     if (!conv) all_conv = false;
+    if (l + 1 < a.k) store_regrows<BT, NV, RR>(R, Bg, a.ldb, cr, nreg, d);
 
     // ---- FP64 re-orthogonalisation of v against X[:, 0..l)
     const int P = l + 1;  // c_j = X[:, j] . v (j < l) and ||v||^2 (j = l)
@@ -366,7 +530,7 @@ __global__ __launch_bounds__(256) void power_kernel(PowerArgs a) {
     ++epoch;
     {
       uint64_t* pb = a.pex + (int64_t)(np & 1) * G * a.pw; np++;
-      if (!allreduce_blocks(pb, a.pw, G, epoch, kvals, P, ktot, scratch, flag, a.spin_limit)) { err = ERR_SPIN; break; }
+      if (!allreduce_blocks(pb, a.pw, b, G, epoch, kvals, P, ktot, scratch, flag, a.spin_limit)) { err = ERR_SPIN; break; }
     }
     for (int i = tid; i < nrows; i += 256) {
       double v = vv[i];
@@ -384,7 +548,7 @@ __global__ __launch_bounds__(256) void power_kernel(PowerArgs a) {
     ++epoch;
     {
       uint64_t* pb = a.pex + (int64_t)(np & 1) * G * a.pw; np++;
-      if (!allreduce_blocks(pb, a.pw, G, epoch, sv + 2, 1, st + 4, scratch, flag, a.spin_limit)) { err = ERR_SPIN; break; }
+      if (!allreduce_blocks(pb, a.pw, b, G, epoch, sv + 2, 1, st + 4, scratch, flag, a.spin_limit)) { err = ERR_SPIN; break; }
     }
     const double vn2 = st[4];
     if (!isfinite(vn2)) { err = ERR_NONFINITE; break; }
@@ -400,12 +564,11 @@ __global__ __launch_bounds__(256) void power_kernel(PowerArgs a) {
 
     // ---- deflation: w = B v, alpha = v.w, B <- B - v w^T - w v^T + alpha v v^T
     ++epoch;
-    {
-      uint64_t* vb = a.vex + (int64_t)(l & 1) * 2 * dpad;
-      for (int i = tid; i < nrows; i += 256) ll_store_f64(vb + 2 * (int64_t)(r0 + i), epoch, vv[i]);
-      if (!gather_f64_as<BT>(vb, epoch, d, xs, flag, a.spin_limit)) { err = ERR_SPIN; break; }
-    }
-    gemv_own<BT>(a, Bs, Bg, nrows, xs, wv);
+    uint64_t* vb = a.vex + (int64_t)(l & 1) * a.vstride;
+    for (int i = tid; i < nrows; i += 256) ll_store_f64(vb + 2 * (int64_t)(r0 + i), epoch, vv[i]);
+    if (!gather_f64_as<BT>(vb, epoch, d, xs, flag, a.spin_limit)) { err = ERR_SPIN; break; }
+    gemv_range<BT>(Bs, a.ldsB, 0, cr, xs, d, true, wv);
+    gemv_range<BT>(Bg, a.ldb, cr, nrows, xs, d, a.vec_ok != 0, wv);
     __syncthreads();
     if (tid == 0) {
       double al = 0.0;
@@ -414,27 +577,24 @@ __global__ __launch_bounds__(256) void power_kernel(PowerArgs a) {
     }
     __syncthreads();
     ++epoch;
+    const uint32_t wep = epoch;
+    uint64_t* wb = a.wex + (int64_t)(l & 1) * a.vstride;
+    for (int i = tid; i < nrows; i += 256) ll_store_f64(wb + 2 * (int64_t)(r0 + i), wep, wv[i]);
     {
-      uint64_t* wb = a.wex + (int64_t)(l & 1) * 2 * dpad;
-      for (int i = tid; i < nrows; i += 256) ll_store_f64(wb + 2 * (int64_t)(r0 + i), epoch, wv[i]);
       uint64_t* pb = a.pex + (int64_t)(np & 1) * G * a.pw; np++;
-      if (!allreduce_blocks(pb, a.pw, G, epoch, sv + 3, 1, st + 5, scratch, flag, a.spin_limit)) { err = ERR_SPIN; break; }
-      if (!gather_f64_as<BT>(wb, epoch, d, aux, flag, a.spin_limit)) { err = ERR_SPIN; break; }
+      if (!allreduce_blocks(pb, a.pw, b, G, epoch, sv + 3, 1, st + 5, scratch, flag, a.spin_limit)) { err = ERR_SPIN; break; }
     }
     const double alpha = st[5];
-    // own-row update, LDS rows then HBM rows
-    for (int li = 0; li < nrows; li++) {
-      const double vi = vv[li], wi = wv[li];
-      BT* row = li < cr ? Bs + (int64_t)li * a.ldsB : Bg + (int64_t)li * a.ldb;
-      for (int c = tid; c < d; c += 256) {
-        const double vc = (double)xs[c], wc = (double)aux[c];
-        double x = (double)row[c];
-        x = fma(-vi, wc, x);
-        x = fma(-wi, vc, x);
-        x = fma(alpha * vi, vc, x);
-        row[c] = (BT)x;
-      }
-    }
+    // Own-row update B <- B - beta v^T - v w^T with beta = w - alpha v, in two
+    // phases that each read one vector from LDS: first with xs = v, then with
+    // xs = w (gathered from the published words).  Each phase is done in FP64
+    // and rounded to B's type.
+    for (int i = tid; i < nrows; i += 256) xv[i] = wv[i] - alpha * vv[i];  // beta (own rows)
+    __syncthreads();
+    deflate_rows<BT>(a, Bs, Bg, cr, nrows, xs, xv);
+    __syncthreads();
+    if (!gather_f64_as<BT>(wb, wep, d, xs, flag, a.spin_limit)) { err = ERR_SPIN; break; }
+    deflate_rows<BT>(a, Bs, Bg, cr, nrows, xs, vv);
     __syncthreads();
   }
 
@@ -446,12 +606,49 @@ __global__ __launch_bounds__(256) void power_kernel(PowerArgs a) {
   if (err != ERR_NONE && tid == 0) atomicMax(a.status + 2, err);
 }
 
+// Single problem: the whole grid is one team.
+template <typename BT, int NV, int RR>
+__global__ __launch_bounds__(256, 1) void power_kernel(PowerArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  uint32_t epoch = 0, nx = 0, np = 0;
+  solve_problem<BT, NV, RR>(a, blockIdx.x, gridDim.x, smem, epoch, nx, np);
+}
+
+// Batch of problems: the grid is split into teams (contiguous workgroup
+// ranges); each team solves its list of problems one after the other, with
+// its own exchange buffers.  Teams never wait on each other.
+__global__ __launch_bounds__(256, 1) void power_team_kernel(const PowerArgs* probs, const int* order,
+                                                            const PowerTeam* teams, const int* team_of_block) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int t = team_of_block[blockIdx.x];
+  if (t < 0) return;
+  const PowerTeam td = teams[t];
+  const int b = blockIdx.x - td.first;
+  uint32_t epoch = 0, nx = 0, np = 0;
+  for (int i = td.pbegin; i < td.pend; i++) {
+    PowerArgs a = probs[order[i]];
+    a.xex = td.xex; a.pex = td.pex; a.vex = td.vex; a.wex = td.wex; a.kscr = td.kscr;
+    a.pw = td.pw; a.xwords = td.xwords; a.vstride = td.vstride;
+    solve_problem<float, 0, 0>(a, b, td.size, smem, epoch, nx, np);
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
 static size_t power_lds_fixed(int rpb, int dpad, int elem) {
   const int rpbA = (rpb + 1) & ~1;
-  return (size_t)(4 * rpbA + 256 + 8 + 8 + 18) * 8 + (size_t)2 * dpad * elem;
+  return (size_t)(4 * rpbA + 256 + 8 + 8 + 18) * 8 + (size_t)dpad * elem;
+}
+
+// register-row configuration for an FP32 Gram of dimension d
+static void reg_config(int d, int* NV, int* RR) {
+  if (d <= 1024) { *NV = 4; *RR = 4; }
+  else if (d <= 2048) { *NV = 8; *RR = 4; }
+  else if (d <= 4096) { *NV = 16; *RR = 2; }
+  else if (d <= 8192) { *NV = 32; *RR = 1; }
+  else { *NV = 0; *RR = 0; }
 }
 
 int power_plan(int dtype_bytes, int d, int k, int num_cu, size_t max_lds, int max_blocks_hint, PowerPlan* p) {
@@ -465,7 +662,7 @@ int power_plan(int dtype_bytes, int d, int k, int num_cu, size_t max_lds, int ma
   const int dpad = (d + 3) & ~3;
   p->ldsB = dpad;
   const size_t fixed = power_lds_fixed(p->rpb, dpad, dtype_bytes);
-  if (fixed > max_lds) return -1;  // vector does not fit in LDS
+  if (fixed > max_lds) return -1;  // the iterate does not fit in LDS
   const size_t row_bytes = (size_t)dpad * dtype_bytes;
   int cache = (int)((max_lds - fixed) / row_bytes);
   if (cache > p->rpb) cache = p->rpb;
@@ -485,13 +682,28 @@ __global__ void zero_words_kernel(uint64_t* p, size_t n) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0;
 }
 
+static const void* pick_kernel(int is_f64, int d) {
+  if (is_f64) return (const void*)power_kernel<double, 0, 0>;
+  int NV, RR;
+  reg_config(d, &NV, &RR);
+  switch (NV) {
+    case 4: return (const void*)power_kernel<float, 4, 4>;
+    case 8: return (const void*)power_kernel<float, 8, 4>;
+    case 16: return (const void*)power_kernel<float, 16, 2>;
+    case 32: return (const void*)power_kernel<float, 32, 1>;
+    default: return (const void*)power_kernel<float, 0, 0>;
+  }
+}
+
 int power_launch(int is_f64, const PowerPlan& p, PowerArgs a, hipStream_t stream) {
   const size_t total = p.xex_words + p.pex_words + p.vex_words + p.wex_words;
   hipLaunchKernelGGL(zero_words_kernel, dim3(256), dim3(256), 0, stream, a.xex, total);
   TSVD_HIP_TRY(hipGetLastError());
   a.rpb = p.rpb; a.cache_rows = p.cache_rows; a.ldsB = p.ldsB; a.pw = p.pw;
+  a.xwords = (int64_t)p.ldsB * (is_f64 ? 2 : 1);
+  a.vstride = (int64_t)2 * p.ldsB;
   void* args[] = {&a};
-  const void* fn = is_f64 ? (const void*)power_kernel<double> : (const void*)power_kernel<float>;
+  const void* fn = pick_kernel(is_f64, a.d);
   TSVD_HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_bytes));
   int per_cu = 0;
   TSVD_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, p.lds_bytes));

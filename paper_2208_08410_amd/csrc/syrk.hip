@@ -201,14 +201,13 @@ __device__ __forceinline__ void store_panel_elem(typename SyrkCfg<MODE>::AT* s,
 // Partial-tile kernel
 // ---------------------------------------------------------------------------
 template <int MODE, int SIDE>
-__global__ __launch_bounds__(256) void syrk_partial_kernel(SyrkArgs a) {
+__device__ __forceinline__ void syrk_unit(const SyrkArgs& a, int s, int t) {
   using Cfg = SyrkCfg<MODE>;
   using AT = typename Cfg::AT;
   using OT = typename Cfg::OT;
   constexpr int BM = Cfg::BM, BK = Cfg::BK, LDK = Cfg::LDK;
 
-  int s, t, ti, tj;
-  unit_of(a, blockIdx.x, s, t);
+  int ti, tj;
   tri_tile(t, ti, tj);
   const bool diag = (ti == tj);
   const int64_t k0 = (int64_t)s * a.kchunk;
@@ -436,6 +435,175 @@ __global__ __launch_bounds__(256) void syrk_partial_kernel(SyrkArgs a) {
   }
 }
 
+template <int MODE, int SIDE>
+__global__ __launch_bounds__(256) void syrk_partial_kernel(SyrkArgs a) {
+  int s, t;
+  unit_of(a, blockIdx.x, s, t);
+  syrk_unit<MODE, SIDE>(a, s, t);
+}
+
+// ---------------------------------------------------------------------------
+// BF16X3 partial tiles of 256 x 256 with 8 waves (2 x 4, each 128 x 64 as
+// 4 x 2 MFMA 32x32x16 blocks).  Per k-step a wave reads 12 fragments for 24
+// MFMAs (half the LDS traffic per MFMA of the 128-tile kernel); the two LDS
+// stages take the whole 160 KB, so one workgroup runs per CU.
+// ---------------------------------------------------------------------------
+constexpr int BIG_BM = 256, BIG_BK = 32, BIG_LDK = BIG_BK + 8;
+constexpr size_t BIG_LDS = (size_t)2 * 2 * 2 * BIG_BM * BIG_LDK * 2;  // stages x panels x hi/lo x rows x LDK x 2 B
+
+template <int SIDE>
+__device__ __forceinline__ void big_load(const SyrkArgs& a, int64_t c0, int64_t k0, int64_t kend, float (&v)[4][4]) {
+  const float* A = (const float*)a.A;
+  const int tid = threadIdx.x;
+  if (SIDE == 0) {
+    const int rg = tid & 7, cg = tid >> 3;  // 8 row groups x 64 column groups
+    const int64_t c = c0 + 4 * cg;
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      const int64_t k = k0 + 4 * rg + j;
+      const float* p = A + k * a.lda + c;
+      if (k < kend && a.vec_ok && c + 3 < a.d) {
+        const float4 f = *(const float4*)p;
+        v[j][0] = f.x; v[j][1] = f.y; v[j][2] = f.z; v[j][3] = f.w;
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; i++) v[j][i] = (k < kend && c + i < a.d) ? p[i] : 0.0f;
+      }
+    }
+  } else {
+    const int kg = tid & 7, rr = tid >> 3;  // 8 k groups x 64 rows (x 4 passes)
+    const int64_t k = k0 + 4 * kg;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      const int64_t c = c0 + rr + 64 * q;
+      const float* p = A + c * a.lda + k;
+      if (c < a.d && a.vec_ok && k + 3 < kend) {
+        const float4 f = *(const float4*)p;
+        v[q][0] = f.x; v[q][1] = f.y; v[q][2] = f.z; v[q][3] = f.w;
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; i++) v[q][i] = (c < a.d && k + i < kend) ? p[i] : 0.0f;
+      }
+    }
+  }
+}
+
+template <int SIDE>
+__device__ __forceinline__ void big_store(__bf16* hi, __bf16* lo, const float (&v)[4][4]) {
+  const int tid = threadIdx.x;
+  if (SIDE == 0) {
+    const int rg = tid & 7, cg = tid >> 3;
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      bf16x4 h, l;
+#pragma unroll
+      for (int j = 0; j < 4; j++) { __bf16 x, y; split_bf16(v[j][i], x, y); h[j] = x; l[j] = y; }
+      const int off = (4 * cg + i) * BIG_LDK + 4 * rg;
+      *(bf16x4*)(hi + off) = h;
+      *(bf16x4*)(lo + off) = l;
+    }
+  } else {
+    const int kg = tid & 7, rr = tid >> 3;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      bf16x4 h, l;
+#pragma unroll
+      for (int j = 0; j < 4; j++) { __bf16 x, y; split_bf16(v[q][j], x, y); h[j] = x; l[j] = y; }
+      const int off = (rr + 64 * q) * BIG_LDK + 4 * kg;
+      *(bf16x4*)(hi + off) = h;
+      *(bf16x4*)(lo + off) = l;
+    }
+  }
+}
+
+template <int SIDE>
+__global__ __launch_bounds__(512, 1) void syrk_bf16x3_big_kernel(SyrkArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __bf16* lds = (__bf16*)smem;  // [stage][panel][hi/lo][BM * LDK]
+  auto at = [&](int stage, int panel, int part) { return lds + ((stage * 2 + panel) * 2 + part) * BIG_BM * BIG_LDK; };
+  int s, t, ti, tj;
+  unit_of(a, blockIdx.x, s, t);
+  tri_tile(t, ti, tj);
+  const bool diag = (ti == tj);
+  const int64_t k0 = (int64_t)s * a.kchunk;
+  const int64_t kend = k0 + a.kchunk < a.K ? k0 + a.kchunk : a.K;
+  const int64_t cI = (int64_t)ti * BIG_BM, cJ = (int64_t)tj * BIG_BM;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 2, wn = wave & 3;  // 2 x 4 waves, each 128 x 64
+  float* out = (float*)a.partial + ((int64_t)s * a.T + t) * BIG_BM * BIG_BM;
+  const int nk = (int)((kend - k0 + BIG_BK - 1) / BIG_BK);
+
+  floatx16 acc[4][2];
+#pragma unroll
+  for (int i = 0; i < 4; i++)
+#pragma unroll
+    for (int j = 0; j < 2; j++)
+#pragma unroll
+      for (int e = 0; e < 16; e++) acc[i][j][e] = 0.0f;
+
+  float vi[4][4], vj[4][4];
+  if (nk > 0) {
+    big_load<SIDE>(a, cI, k0, kend, vi);
+    if (!diag) big_load<SIDE>(a, cJ, k0, kend, vj);
+    big_store<SIDE>(at(0, 0, 0), at(0, 0, 1), vi);
+    if (!diag) big_store<SIDE>(at(0, 1, 0), at(0, 1, 1), vj);
+  }
+  __syncthreads();
+  for (int kt = 0; kt < nk; kt++) {
+    const int cur = kt & 1;
+    const bool more = kt + 1 < nk;
+    if (more) {
+      const int64_t kb = k0 + (int64_t)(kt + 1) * BIG_BK;
+      big_load<SIDE>(a, cI, kb, kend, vi);
+      if (!diag) big_load<SIDE>(a, cJ, kb, kend, vj);
+    }
+    const __bf16* Ih = at(cur, 0, 0);
+    const __bf16* Il = at(cur, 0, 1);
+    const __bf16* Jh = diag ? Ih : at(cur, 1, 0);
+    const __bf16* Jl = diag ? Il : at(cur, 1, 1);
+#pragma unroll
+    for (int ks = 0; ks < BIG_BK; ks += 16) {
+      bf16x8 ah[4], al[4], bh[2], bl[2];
+      const int kofs = ks + 8 * (lane >> 5);
+#pragma unroll
+      for (int i = 0; i < 4; i++) {
+        const int r = wm * 128 + i * 32 + (lane & 31);
+        ah[i] = *(const bf16x8*)(Ih + r * BIG_LDK + kofs);
+        al[i] = *(const bf16x8*)(Il + r * BIG_LDK + kofs);
+      }
+#pragma unroll
+      for (int j = 0; j < 2; j++) {
+        const int c = wn * 64 + j * 32 + (lane & 31);
+        bh[j] = *(const bf16x8*)(Jh + c * BIG_LDK + kofs);
+        bl[j] = *(const bf16x8*)(Jl + c * BIG_LDK + kofs);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int j = 0; j < 2; j++) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+        }
+    }
+    if (more) {
+      big_store<SIDE>(at(cur ^ 1, 0, 0), at(cur ^ 1, 0, 1), vi);
+      if (!diag) big_store<SIDE>(at(cur ^ 1, 1, 0), at(cur ^ 1, 1, 1), vj);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; i++)
+#pragma unroll
+    for (int j = 0; j < 2; j++)
+#pragma unroll
+      for (int e = 0; e < 16; e++) {
+        const int r = wm * 128 + i * 32 + (e >> 2) * 8 + (lane >> 5) * 4 + (e & 3);
+        const int c = wn * 64 + j * 32 + (lane & 31);
+        out[r * BIG_BM + c] = acc[i][j][e];
+      }
+}
+
 // ---------------------------------------------------------------------------
 // Reduction of chunk partials into the full symmetric B.
 // One workgroup per 32x32 sub-tile of a triangle tile; sums the S partials in
@@ -444,11 +612,11 @@ __global__ __launch_bounds__(256) void syrk_partial_kernel(SyrkArgs a) {
 // skipped; on diagonal sub-tiles only the lower half is taken from the sums.
 // ---------------------------------------------------------------------------
 template <typename OT, int BM>
-__global__ __launch_bounds__(256) void syrk_reduce_kernel(const OT* partial, int T, int S, int64_t d, OT* B,
-                                                          int64_t ldb, int accumulate) {
+__device__ __forceinline__ void syrk_reduce_unit(const OT* partial, int T, int S, int64_t d, OT* B, int64_t ldb,
+                                                 int accumulate, int unit) {
   constexpr int SUB = BM / 32;
-  const int t = blockIdx.x / (SUB * SUB);
-  const int sub = blockIdx.x % (SUB * SUB);
+  const int t = unit / (SUB * SUB);
+  const int sub = unit % (SUB * SUB);
   const int sr = sub / SUB, sc = sub % SUB;
   int ti, tj;
   tri_tile(t, ti, tj);
@@ -483,11 +651,79 @@ __global__ __launch_bounds__(256) void syrk_reduce_kernel(const OT* partial, int
   }
 }
 
+template <typename OT, int BM>
+__global__ __launch_bounds__(256) void syrk_reduce_kernel(const OT* partial, int T, int S, int64_t d, OT* B,
+                                                          int64_t ldb, int accumulate) {
+  syrk_reduce_unit<OT, BM>(partial, T, S, d, B, ldb, accumulate, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Grouped Gram for a batch of problems (128 tiles, FP32 or BF16X3): workgroup
+// ids are dealt to problems by prefix sums of their unit counts.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int find_job(const GramJob* jobs, int njobs, int64_t u, bool reduce) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if ((reduce ? jobs[mid].rbegin : jobs[mid].ubegin) <= u) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ SyrkArgs job_args(const GramJob& j) {
+  SyrkArgs a;
+  a.A = j.A; a.m = j.m; a.n = j.n; a.lda = j.lda;
+  a.d = j.side == 0 ? j.n : j.m;
+  a.K = j.side == 0 ? j.m : j.n;
+  a.kchunk = j.kchunk; a.nt = j.nt; a.T = j.T; a.S = j.S; a.xcd_map = 0;
+  a.vec_ok = j.vec_ok;
+  a.partial = j.partial;
+  return a;
+}
+
+// all jobs of one launch share the side (one LDS layout per kernel)
+template <int MODE, int SIDE>
+__global__ __launch_bounds__(256) void syrk_grouped_kernel(const GramJob* jobs, int njobs) {
+  const int jb = find_job(jobs, njobs, blockIdx.x, false);
+  const GramJob& j = jobs[jb];
+  const SyrkArgs a = job_args(j);
+  const int u = (int)(blockIdx.x - j.ubegin);
+  syrk_unit<MODE, SIDE>(a, u / j.T, u % j.T);
+}
+
+__global__ __launch_bounds__(256) void syrk_grouped_reduce_kernel(const GramJob* jobs, int njobs) {
+  const int jb = find_job(jobs, njobs, blockIdx.x, true);
+  const GramJob& j = jobs[jb];
+  syrk_reduce_unit<float, 128>((const float*)j.partial, j.T, j.S, j.side == 0 ? j.n : j.m, (float*)j.B, j.ldb, 0,
+                               (int)(blockIdx.x - j.rbegin));
+}
+
+int syrk_grouped_launch(int mode, int side, const GramJob* d_jobs, int njobs, int64_t units, int64_t runits,
+                        hipStream_t s) {
+  if (njobs <= 0) return 0;
+  const dim3 g((unsigned)units), blk(256);
+  if (mode == MODE_BF16X3) {
+    if (side == 0) hipLaunchKernelGGL((syrk_grouped_kernel<MODE_BF16X3, 0>), g, blk, 0, s, d_jobs, njobs);
+    else hipLaunchKernelGGL((syrk_grouped_kernel<MODE_BF16X3, 1>), g, blk, 0, s, d_jobs, njobs);
+  } else {
+    if (side == 0) hipLaunchKernelGGL((syrk_grouped_kernel<MODE_FP32, 0>), g, blk, 0, s, d_jobs, njobs);
+    else hipLaunchKernelGGL((syrk_grouped_kernel<MODE_FP32, 1>), g, blk, 0, s, d_jobs, njobs);
+  }
+  TSVD_HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(syrk_grouped_reduce_kernel, dim3((unsigned)runits), dim3(256), 0, s, d_jobs, njobs);
+  TSVD_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
 // ---------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------
-int syrk_plan(int mode, int64_t d, int64_t K, int64_t rows_per_block, int num_cu, SyrkPlan* p) {
-  const int BM = (mode == MODE_FP64) ? 64 : 128;
+int syrk_plan(int mode, int64_t d, int64_t K, int64_t rows_per_block, int num_cu, SyrkPlan* p, int tile,
+              int chunks) {
+  // BF16X3 uses 256-wide tiles for large Grams unless told otherwise
+  if (mode == MODE_BF16X3 && tile == 0) tile = d >= 1024 ? 256 : 128;
+  const int BM = (mode == MODE_FP64) ? 64 : (mode == MODE_BF16X3 && tile == 256 ? 256 : 128);
   const int BK = (mode == MODE_FP64) ? 16 : 32;
   p->BM = BM;
   p->nt = (int)((d + BM - 1) / BM);
@@ -495,8 +731,10 @@ int syrk_plan(int mode, int64_t d, int64_t K, int64_t rows_per_block, int num_cu
   int64_t S;
   if (rows_per_block > 0) {
     S = (K + rows_per_block - 1) / rows_per_block;
+  } else if (chunks > 0) {
+    S = chunks;
   } else {
-    const int64_t target = 4 * (int64_t)num_cu;
+    const int64_t target = (BM == 256 ? 8 : 4) * (int64_t)num_cu;  // workgroups per CU: 1 for 256 tiles, 2 else
     S = (target + p->T - 1) / p->T;
     S = ((S + 7) / 8) * 8;
     const int64_t maxS = (K + 4 * BK - 1) / (4 * BK);  // at least 4 k-stages per chunk
@@ -527,7 +765,12 @@ int syrk_launch(int mode, int side, const void* A, int64_t m, int64_t n, int64_t
   a.vec_ok = (((uintptr_t)A & 15) == 0) && (lda % 4 == 0);
   a.partial = partial;
   const int grid = p.T * p.S;
-  if (mode == MODE_BF16X3) {
+  if (mode == MODE_BF16X3 && p.BM == 256) {
+    const void* fn = side == 0 ? (const void*)syrk_bf16x3_big_kernel<0> : (const void*)syrk_bf16x3_big_kernel<1>;
+    TSVD_HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)BIG_LDS));
+    if (side == 0) hipLaunchKernelGGL((syrk_bf16x3_big_kernel<0>), dim3(grid), dim3(512), BIG_LDS, stream, a);
+    else hipLaunchKernelGGL((syrk_bf16x3_big_kernel<1>), dim3(grid), dim3(512), BIG_LDS, stream, a);
+  } else if (mode == MODE_BF16X3) {
     if (side == 0) hipLaunchKernelGGL((syrk_partial_kernel<MODE_BF16X3, 0>), dim3(grid), dim3(256), 0, stream, a);
     else hipLaunchKernelGGL((syrk_partial_kernel<MODE_BF16X3, 1>), dim3(grid), dim3(256), 0, stream, a);
   } else if (mode == MODE_FP32) {
@@ -543,6 +786,9 @@ int syrk_launch(int mode, int side, const void* A, int64_t m, int64_t n, int64_t
   if (mode == MODE_FP64)
     hipLaunchKernelGGL((syrk_reduce_kernel<double, 64>), dim3(rgrid), dim3(256), 0, stream, (const double*)partial,
                        p.T, p.S, a.d, (double*)B, ldb, accumulate);
+  else if (p.BM == 256)
+    hipLaunchKernelGGL((syrk_reduce_kernel<float, 256>), dim3(rgrid), dim3(256), 0, stream, (const float*)partial,
+                       p.T, p.S, a.d, (float*)B, ldb, accumulate);
   else
     hipLaunchKernelGGL((syrk_reduce_kernel<float, 128>), dim3(rgrid), dim3(256), 0, stream, (const float*)partial,
                        p.T, p.S, a.d, (float*)B, ldb, accumulate);

@@ -24,7 +24,9 @@ def exact_split(m, n, seed):
 
 # shapes: ragged tiles (not multiples of 128/64), a single column/row, chunking
 SHAPES = [(1000, 300, "right", 0), (1000, 300, "right", 96), (257, 1000, "left", 0), (1700, 129, "right", 64),
-          (5, 1, "right", 0), (1, 5, "left", 0), (64, 64, "right", 0), (333, 700, "right", 0)]
+          (5, 1, "right", 0), (1, 5, "left", 0), (64, 64, "right", 0), (333, 700, "right", 0),
+          # d >= 1024: the 256-wide BF16X3 tiles (ragged last tile, both sides)
+          (1700, 1100, "right", 0), (1300, 1030, "left", 0), (1024, 1024, "right", 320)]
 
 
 @pytest.mark.parametrize("m,n,side,rpb", SHAPES)
@@ -85,3 +87,24 @@ def test_lda_padding_and_misaligned(ctx):
     assert np.array_equal(B.cpu().numpy().astype(np.float64), A.T @ A)
     B = P.tsvd_gram_dense(ctx, big[:, 1:131], gram="fp32", side="left")
     assert np.array_equal(B.cpu().numpy().astype(np.float64), A @ A.T)
+
+
+@pytest.mark.parametrize("tile", [128, 256])
+def test_tuning_tiles_agree(ctx, tile):
+    """Both BF16X3 tile shapes give the mode's definition bit for bit."""
+    A = exact_split(1500, 700, seed=21)
+    ref = O.gram_bf16x3(A)
+    P.set_tuning(ctx, gram_tile=tile, gram_chunks=5)
+    try:
+        B = P.tsvd_gram_dense(ctx, to_dev(A), gram="bf16x3").cpu().numpy()
+    finally:
+        P.set_tuning(ctx)
+    assert np.array_equal(B.astype(np.float64), ref)
+
+
+def test_tuning_rejects_bad_values(ctx):
+    with pytest.raises(P.TsvdError):
+        P.set_tuning(ctx, gram_tile=64)
+    with pytest.raises(P.TsvdError):
+        P.set_tuning(ctx, power_blocks=100000)
+    assert P.get_tuning(ctx) == {"gram_tile": 0, "gram_chunks": 0, "power_blocks": 0}

@@ -1,0 +1,60 @@
+"""Dense t-SVD with A in pinned host memory (double-buffered H2D row batches)."""
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2208_08410_amd as P
+import synth
+from gpu_util import line_angle, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def pinned(x):
+    import torch
+    t = torch.empty(x.shape, dtype=torch.float32, pin_memory=True)
+    t.copy_(torch.from_numpy(np.ascontiguousarray(x)))
+    return t
+
+
+@pytest.mark.parametrize("rpb,q,gram", [(3072, 2, "bf16x3"), (2048, 3, "fp32"), (768, 2, "bf16x3"), (20480, 2, "fp32")])
+def test_pinned_bitwise_equals_device(ctx, rpb, q, gram):
+    """Streaming the rows in batches of rpb (a multiple of 128, the finishing
+    pass's row tile) with one Gram chunk per batch gives the same bits as the
+    in-HBM path with the same row blocking; the last batch is ragged."""
+    m, n, k = 20000, 384, 6
+    dk = synth.dense_known(m, n, synth.spectrum_geometric(0.9, n), seed=3, dtype=np.float32)
+    st = to_dev(synth.start_vectors(k, n, seed=2))
+    Ud, Sd, Vd, infd = P.tsvd_dense(ctx, to_dev(dk.A), k, 1e-9, st, gram=gram, rows_per_block=rpb)
+    Up, Sp, Vp, infp = P.tsvd_dense(ctx, pinned(dk.A), k, 1e-9, st, gram=gram, rows_per_block=rpb, queue_depth=q)
+    assert infp["h2d_bytes"] == 2 * m * n * 4
+    assert infp["iters"] == infd["iters"]
+    assert np.array_equal(Sp.cpu().numpy(), Sd.cpu().numpy())
+    assert np.array_equal(Vp.cpu().numpy(), Vd.cpu().numpy())
+    assert np.array_equal(Up.cpu().numpy(), Ud.cpu().numpy())
+
+
+def test_pinned_default_batches_vs_oracle(ctx):
+    m, n, k, eps = 30000, 256, 5, 1e-9
+    dk = synth.dense_known(m, n, synth.spectrum_geometric(0.9, n), seed=4, dtype=np.float32)
+    st = synth.start_vectors(k, n, seed=1)
+    ref = O.tsvd_gram(dk.A, eps, k, st)
+    U, S, V, info = P.tsvd_dense(ctx, pinned(dk.A), k, eps, to_dev(st), fixed_iters=ref.iters)
+    S = S.cpu().numpy(); V = V.cpu().numpy()
+    assert np.max(np.abs(S - ref.S) / ref.S) < 1e-6
+    Vr = O.canonical(ref.U, ref.V)[1]
+    for l in range(k):
+        assert line_angle(V[:, l], Vr[:, l]) < 1e-4
+
+
+def test_pinned_rejects_pageable_and_left_branch(ctx):
+    import torch
+    A = torch.from_numpy(synth.gaussian_dense(100, 50, seed=1))
+    st = to_dev(synth.start_vectors(2, 50, seed=1))
+    with pytest.raises(ValueError):
+        P.tsvd_dense(ctx, A, 2, 1e-8, st)  # pageable memory is refused by the binding
+    Aw = pinned(synth.gaussian_dense(50, 100, seed=1))
+    with pytest.raises(P.TsvdError) as e:
+        P.tsvd_dense(ctx, Aw, 2, 1e-8, to_dev(synth.start_vectors(2, 50, seed=1)))
+    assert e.value.status == P.UNSUPPORTED

@@ -82,3 +82,22 @@ def test_nonfinite_gram(ctx):
     with pytest.raises(P.TsvdError) as e:
         P.tsvd_power_gram(ctx, to_dev(B), 2, 1e-8, to_dev(st))
     assert e.value.status == P.NONFINITE
+
+
+@pytest.mark.parametrize("d,k", [(3999, 3), (4096, 3), (6000, 2)])
+def test_power_fp32_register_rows(ctx, d, k):
+    """Large d: a block's rows are split over LDS, registers and HBM; the
+    result must match the FP64 oracle run for the same number of steps."""
+    g = synth.rng(d, 3)
+    lam = 0.8 ** np.arange(d, dtype=np.float64)
+    Q = synth.haar_orthonormal(d, 8, seed=d, tag=1)
+    # B = Q diag(lam[:8]) Q^T + small symmetric noise: a well-separated top
+    Bn = g.standard_normal((d, d)) * 1e-5
+    B0 = (Q * lam[:8]) @ Q.T + (Bn + Bn.T)
+    st = synth.start_vectors(k, d, seed=5)
+    ref = O.tsvd_gram(np.eye(d), 1e-9, k, st, B0=B0, max_iter=2000)
+    X, info = P.tsvd_power_gram(ctx, to_dev(B0.astype(np.float32)), k, 1e-9, to_dev(st), fixed_iters=ref.iters)
+    X = X.cpu().numpy()
+    for l in range(k):
+        assert line_angle(X[:, l], ref.V[:, l]) < 1e-5
+    assert np.allclose(info["lambda"], ref.lam, rtol=1e-5)
