@@ -12,6 +12,12 @@ against the closed-form s after the run.
 Prints ONE JSON line with the headline metric (triplets/s), the roofline of
 the dominant kernel, the Gram kernel's MFMA roofline, and a CPU baseline (the
 FP64 oracle timed on a bounded sample of the same workload).
+
+``--workload serve`` measures the serving loop instead: Poisson arrivals of
+dense t-SVD requests (m log-uniform in [1024, 65536], n in [128, 4096], k in
+{8, 16, 32, 64}, s_i = 0.95^i) drawn from a pool of pre-generated matrices,
+served by the library's request server (continuous batching, admission by
+device footprint); it prints p50/p99 latency and the achieved request rate.
 """
 
 from __future__ import annotations
@@ -47,6 +53,14 @@ def parse():
     ap.add_argument("--compare-fp32", type=int, default=1, help="also time the plain FP32 Gram mode")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--workload", default="dense", choices=["dense", "serve"])
+    ap.add_argument("--rate", type=float, default=200.0, help="serve: mean arrivals per second")
+    ap.add_argument("--window", type=float, default=20.0, help="serve: seconds of measured arrivals")
+    ap.add_argument("--warm", type=float, default=2.0, help="serve: seconds of arrivals before the window")
+    ap.add_argument("--pool", type=int, default=48, help="serve: distinct pre-generated matrices")
+    ap.add_argument("--pool-loc", default="host", choices=["host", "device"],
+                    help="serve: pool in pinned host memory (copied per request) or in HBM")
+    ap.add_argument("--budget-gb", type=float, default=64.0, help="serve: server device budget")
     return ap.parse_args()
 
 
@@ -99,12 +113,161 @@ def cpu_baseline(A_dev, s, k, eps, seed):
     }
 
 
+def serve_cpu_baseline(shapes, ks, eps, seed):
+    """Saturation throughput of the FP64 oracle serving the same request mix
+    one request at a time: the Gram rate, the Gram-vector product rate and the
+    u = A v rate are timed on a sample problem, then the mean request time is
+    predicted for the actual shapes and k (with the GPU's iteration counts)."""
+    import numpy as np
+    import oracle as O
+    import synth
+
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 0) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    m0, n0 = 16384, 1024
+    A = synth.gaussian_dense(m0, n0, seed=seed).astype(np.float64)
+    t0 = time.perf_counter()
+    B = O.gram_rowblocks(A)
+    t_gram = time.perf_counter() - t0
+    gram_rate = m0 * n0 * n0 / t_gram
+    st = synth.start_vectors(1, n0, seed=seed)
+    t0 = time.perf_counter()
+    r = O.tsvd_gram(A, 0.0, 1, st, B0=B, max_iter=200)
+    t_pow = time.perf_counter() - t0
+    gemv_rate = 200 * n0 * n0 / t_pow
+    t0 = time.perf_counter()
+    for _ in range(5):
+        A @ r.V[:, 0]
+    fin_rate = 5 * m0 * n0 / (time.perf_counter() - t0)
+    per = []
+    for (m, n), (k, its) in zip(shapes, ks):
+        d, K = min(m, n), max(m, n)
+        per.append(K * d * d / gram_rate + its * d * d / gemv_rate + k * m * n / fin_rate)
+    mean_s = float(np.mean(per))
+    return {
+        "value": 1.0 / mean_s,
+        "unit": "req/s",
+        "cores": int(cores),
+        "kind": "oracle",
+        "sample": (f"FP64 NumPy oracle rates timed on a {m0}x{n0} problem (Gram {gram_rate/1e9:.1f} G mul-add/s, "
+                   f"power step {gemv_rate/1e9:.2f} G/s, u = A v {fin_rate/1e9:.2f} G/s), applied to the served "
+                   f"shapes, k and iteration counts: mean {mean_s:.2f} s per request, one request at a time"),
+    }
+
+
+def serve_main(a):
+    """Serving workload: Poisson arrivals into the library's request server."""
+    import numpy as np
+    import torch
+
+    import paper_2208_08410_amd as P
+    import synth
+
+    dev = torch.device("cuda:0")
+    q = 0.95
+    eps = a.eps
+    g = synth.rng(a.seed, 77)
+    # the pool: log-uniform shapes, A = H_L [diag(q^i); 0] H_R
+    t0 = time.time()
+    pool = []
+    for j in range(a.pool):
+        m = int(round(math.exp(g.uniform(math.log(1024), math.log(65536)))))
+        n = int(round(math.exp(g.uniform(math.log(128), math.log(4096)))))
+        s = synth.spectrum_geometric(q, min(m, n))
+        A = synth.householder_known_torch(m, n, s, a.seed * 1000 + j, dev)
+        if a.pool_loc == "host":
+            Ah = torch.empty((m, n), dtype=torch.float32, pin_memory=True)
+            Ah.copy_(A)
+            del A
+            A = Ah
+        d = min(m, n)
+        v0 = torch.from_numpy(synth.start_vectors(64, d, seed=a.seed * 1000 + j)).to(dev)
+        pool.append((A, v0, s))
+    torch.cuda.synchronize()
+    gen_s = time.time() - t0
+    total = a.warm + a.window
+    count = int(a.rate * total * 1.5) + 16
+    arrivals = synth.request_stream(count, a.rate, a.seed)
+    arrivals = [r for r in arrivals if r.t < total]
+    kch = synth.rng(a.seed, 78).choice([8, 16, 32, 64], size=len(arrivals))
+    pick = synth.rng(a.seed, 79).integers(0, a.pool, size=len(arrivals))
+    ctx = P.Context(0)
+    srv = P.Server(ctx, hbm_budget=int(a.budget_gb * (1 << 30)))
+    tickets = []
+    t_start = time.perf_counter()
+    for i, r in enumerate(arrivals):
+        now = time.perf_counter() - t_start
+        if r.t > now:
+            time.sleep(r.t - now)
+        A, v0, s = pool[pick[i]]
+        k = int(kch[i])
+        tickets.append((srv.submit(dict(A=A, k=k, eps=eps, v0=v0[:k], gram="bf16x3")), r.t, i))
+    results = []
+    for tk, t_arr, i in tickets:
+        U, S, V, info = srv.wait(tk)
+        A, v0, s = pool[pick[i]]
+        k = int(kch[i])
+        rel = float(np.max(np.abs(S.cpu().numpy() - s[:k]) / s[:k]))
+        results.append((t_arr, info, rel, k, tuple(A.shape)))
+    t_end = time.perf_counter() - t_start
+    st = srv.stats()
+    srv.close()
+    ctx.close()
+    meas = [x for x in results if x[0] >= a.warm]
+    lat = np.array([x[1]["latency_ms"] for x in meas])
+    ok = all(x[1]["status"] == "TSVD_OK" for x in results)
+    errs = np.array([x[2] for x in meas])
+    out = {
+        "metric": METRIC,
+        "value": float(np.percentile(lat, 99)),
+        "unit": "ms (p99 latency)",
+        "n_gpus": 1,
+        "steps": len(meas),
+        "warmup": len(results) - len(meas),
+        "ms_per_step": float(np.mean(lat)),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16x3/f32acc gram, f64 finish",
+        "data": "synthetic",
+        "config": {"workload": f"serving: Poisson {a.rate:g} req/s for {a.window:g} s after {a.warm:g} s; "
+                               f"m log-uniform [1024, 65536], n [128, 4096], k in {{8,16,32,64}}, s_i = 0.95^i, "
+                               f"pool of {a.pool} matrices in {'pinned host memory' if a.pool_loc == 'host' else 'HBM'}"
+                               f", eps={eps}", "rate": a.rate, "window_s": a.window, "pool": a.pool,
+                   "pool_loc": a.pool_loc, "budget_gb": a.budget_gb},
+        "p50_ms": float(np.percentile(lat, 50)),
+        "p99_ms": float(np.percentile(lat, 99)),
+        "max_ms": float(lat.max()),
+        "requests": len(meas),
+        "offered_rate": a.rate,
+        "achieved_rate": len(results) / t_end,
+        "all_ok": ok,
+        "sigma_rel_err_max": float(errs.max()),
+        "meets_1e-6": bool(errs.max() < 1e-6),
+        "batches": st["batches"],
+        "mean_batch": st["mean_batch"],
+        "peak_bytes": st["peak_bytes"],
+        "gen_seconds": gen_s,
+    }
+    if a.cpu_baseline:
+        shapes = [x[4] for x in meas]
+        ks = [(x[3], int(sum(x[1]["iters"]))) for x in meas]
+        out["cpu_baseline"] = serve_cpu_baseline(shapes, ks, eps, a.seed)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main():
     a = parse()
     if a.gpus != 1:
         print("bench.py: this build runs on one GPU; multi-GPU (N > 1) is not implemented "
               "(the sharding design is described in DESIGN.md).", file=sys.stderr)
         return 2
+    if a.workload == "serve":
+        return serve_main(a)
     import numpy as np
     import torch
 

@@ -101,6 +101,7 @@ typedef struct {
   double t_total_ms;       /* device time of the whole call */
   int64_t workspace_bytes; /* device workspace the call used */
   int64_t h2d_bytes;       /* bytes copied host -> device (pinned-host input) */
+  double latency_ms;       /* server requests: submission -> completion, host clock; else 0 */
 } tsvd_info;
 
 typedef struct tsvd_ctx tsvd_ctx;
@@ -126,7 +127,11 @@ typedef struct {
   int32_t gram_tile;     /* BF16X3 Gram tile edge: 0 (library choice), 128 or 256 */
   int32_t gram_chunks;   /* contraction chunks (split-K) per Gram launch: 0 = library choice */
   int32_t power_blocks;  /* workgroups of the power-iteration launch: 0 = one per CU */
-  int32_t reserved;
+  int32_t team_kib;      /* batched power launch: KiB of a problem's Gram per team workgroup, which
+                            sets the team size (ceil(4 d^2 / (team_kib * 1024)) workgroups);
+                            0 = 128; range [8, 65536] */
+  int32_t group_kchunk;  /* batched Gram: contraction rows per work unit; 0 = 2048; range [32, 2^20] */
+  int32_t reserved[3];
 } tsvd_tuning;
 
 /* Set / read the context's tuning.  INVALID_ARG for out-of-range values. */
@@ -185,6 +190,105 @@ tsvd_status tsvd_finish_dense(tsvd_ctx* ctx, const void* A, int32_t dtype, int64
 tsvd_status tsvd_dense(tsvd_ctx* ctx, const void* A, int32_t dtype, int32_t loc, int64_t m, int64_t n,
                        int64_t lda, const tsvd_opts* opts, double* U, int64_t ldu, double* S, double* V,
                        int64_t ldv, tsvd_info* info, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Many dense problems in one pass (persistent batched kernel)
+ * ------------------------------------------------------------------------- */
+
+/* One problem of a batch: the arguments of tsvd_dense for a DEVICE FP32 A. */
+typedef struct {
+  const void* A;           /* DEVICE, m x n row-major (lda) */
+  int32_t dtype;           /* TSVD_F32 (the only type the batched path takes) */
+  int64_t m, n, lda;
+  tsvd_opts opts;          /* k, eps, max_iter, fixed_iters, v0 (DEVICE), gram (AUTO, FP32 or BF16X3),
+                              branch; rows_per_block, hbm_budget and queue_depth are not used */
+  double* U;               /* DEVICE FP64 m x k column-major (ldu) */
+  int64_t ldu;
+  double* S;               /* DEVICE FP64 k */
+  double* V;               /* DEVICE FP64 n x k column-major (ldv) */
+  int64_t ldv;
+} tsvd_problem;
+
+/* Algorithm 1 for `count` independent problems of any mix of shapes, in three
+ * grouped launches: the Gram of every problem (work units = problem x split-K
+ * chunk x triangle tile, Algorithm 3's block products), one cooperative power
+ * launch in which the CUs are split into teams that each run Algorithm 2 with
+ * deflation on their list of problems, and the FP64 finishing product.  Each
+ * problem's result is what tsvd_dense computes for it, up to the rounding of a
+ * different reduction order.  hbm_budget bounds the workspace of the whole
+ * batch (0 = no limit).  infos (optional, count entries) receive per-problem
+ * k_done, converged, iters, lambda and the batch's phase times; statuses
+ * (optional HOST array of count) receive per-problem statuses.  Synchronises
+ * `stream`.  Returns OK when every problem is OK, else the status of the first
+ * failing problem (argument errors are found before any launch). */
+tsvd_status tsvd_dense_batched(tsvd_ctx* ctx, int32_t count, const tsvd_problem* problems, int64_t hbm_budget,
+                               tsvd_info* infos, int32_t* statuses, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of dense requests
+ * ------------------------------------------------------------------------- */
+
+typedef struct tsvd_server tsvd_server;
+
+typedef struct {
+  int64_t hbm_budget;      /* device bytes the server allocates once and admits requests into (> 0).
+                              1/16 of it (16 MiB..512 MiB, at most half) holds the running batch's
+                              tables; the rest holds admitted requests' workspaces and staged A */
+  int32_t max_slots;       /* requests admitted and not yet completed, at most; 0 = 256 */
+  int32_t max_batch;       /* requests per batch launch, at most; 0 = max_slots */
+} tsvd_server_config;
+
+typedef struct {
+  int64_t submitted, completed, failed, rejected;  /* completed = finished with OK */
+  int64_t batches;         /* batch launches so far */
+  double mean_batch;       /* requests per batch launch */
+  double p50_ms, p99_ms, mean_ms, max_ms; /* submit -> completion latency of finished (not rejected)
+                                             requests, nearest-rank percentiles */
+  int64_t peak_bytes;      /* high-water mark of admitted request footprints */
+  int64_t in_flight;       /* admitted or running now */
+  int64_t waiting;         /* submitted, not yet admitted */
+} tsvd_server_stats;
+
+/* Start a server on ctx's device: one device allocation of cfg->hbm_budget
+ * bytes, two internal streams (compute, host->device copies) and a worker
+ * thread.  The worker owns ctx until tsvd_server_destroy: make no other call
+ * on ctx meanwhile.  Each worker cycle admits waiting requests in arrival
+ * order while a slot is free and the budget covers the request's footprint
+ * (its Gram, split-K partials and finish sums, plus its A when A is in pinned
+ * host memory, which is then copied at once on the copy stream); when the
+ * device is idle it launches every admitted request as one batch (as
+ * tsvd_dense_batched); when that batch completes it frees its memory and
+ * completes its tickets.  Requests arriving while a batch runs are admitted
+ * and copied during it and form the next batch.  A request's result is the
+ * same whether it runs alone or in any mix (its launch shapes depend on it
+ * alone). */
+tsvd_status tsvd_server_create(tsvd_ctx* ctx, const tsvd_server_config* cfg, tsvd_server** out);
+
+/* Queue one request; returns at once with a ticket.  The problem struct is
+ * copied (with opts.fixed_iters); A (loc DEVICE or PINNED_HOST), opts.v0, U, S
+ * and V are borrowed until the ticket completes.  Argument errors are returned
+ * here (INVALID_ARG / UNSUPPORTED); a request whose footprint exceeds the
+ * budget completes with REJECTED.  Thread safe. */
+tsvd_status tsvd_server_submit(tsvd_server* srv, const tsvd_problem* problem, int32_t loc, uint64_t* ticket);
+
+/* Non-blocking: *done = 1 once the ticket completed; then info (optional; its
+ * iters / lambda arrays, if set, receive k entries) and *status (optional) are
+ * filled and the ticket is released.  INVALID_ARG for an unknown ticket. */
+tsvd_status tsvd_server_poll(tsvd_server* srv, uint64_t ticket, int32_t* done, tsvd_info* info, int32_t* status);
+
+/* Block until the ticket completes; fill info and release the ticket.
+ * Returns the request's status. */
+tsvd_status tsvd_server_wait(tsvd_server* srv, uint64_t ticket, tsvd_info* info);
+
+/* Counters and latency percentiles so far. */
+tsvd_status tsvd_server_get_stats(tsvd_server* srv, tsvd_server_stats* stats);
+
+/* Message of the server's last failure ("" if none). */
+const char* tsvd_server_last_error(const tsvd_server* srv);
+
+/* Finish every submitted request, stop the worker, free the device memory.
+ * NULL is ignored. */
+void tsvd_server_destroy(tsvd_server* srv);
 
 /* ---------------------------------------------------------------------------
  * Sparse A (CSR): the implicit deflated product of Equation 2 / Algorithm 4

@@ -26,6 +26,8 @@ __all__ = [
     "tsvd_power_gram",
     "tsvd_finish_dense",
     "tsvd_dense",
+    "tsvd_dense_batched",
+    "Server",
     "set_tuning",
     "get_tuning",
     "Csr",
@@ -84,7 +86,51 @@ class TsvdTuning(ctypes.Structure):
         ("gram_tile", ctypes.c_int32),
         ("gram_chunks", ctypes.c_int32),
         ("power_blocks", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("team_kib", ctypes.c_int32),
+        ("group_kchunk", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
+    ]
+
+
+class TsvdProblem(ctypes.Structure):
+    _fields_ = [
+        ("A", ctypes.c_void_p),
+        ("dtype", ctypes.c_int32),
+        ("m", ctypes.c_int64),
+        ("n", ctypes.c_int64),
+        ("lda", ctypes.c_int64),
+        ("opts", TsvdOpts),
+        ("U", ctypes.c_void_p),
+        ("ldu", ctypes.c_int64),
+        ("S", ctypes.c_void_p),
+        ("V", ctypes.c_void_p),
+        ("ldv", ctypes.c_int64),
+    ]
+
+
+class TsvdServerConfig(ctypes.Structure):
+    _fields_ = [
+        ("hbm_budget", ctypes.c_int64),
+        ("max_slots", ctypes.c_int32),
+        ("max_batch", ctypes.c_int32),
+    ]
+
+
+class TsvdServerStats(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_int64),
+        ("completed", ctypes.c_int64),
+        ("failed", ctypes.c_int64),
+        ("rejected", ctypes.c_int64),
+        ("batches", ctypes.c_int64),
+        ("mean_batch", ctypes.c_double),
+        ("p50_ms", ctypes.c_double),
+        ("p99_ms", ctypes.c_double),
+        ("mean_ms", ctypes.c_double),
+        ("max_ms", ctypes.c_double),
+        ("peak_bytes", ctypes.c_int64),
+        ("in_flight", ctypes.c_int64),
+        ("waiting", ctypes.c_int64),
     ]
 
 
@@ -102,6 +148,7 @@ class TsvdInfo(ctypes.Structure):
         ("t_total_ms", ctypes.c_double),
         ("workspace_bytes", ctypes.c_int64),
         ("h2d_bytes", ctypes.c_int64),
+        ("latency_ms", ctypes.c_double),
     ]
 
 
@@ -142,6 +189,24 @@ def load_library():
     lib.tsvd_dense.argtypes = [vp, vp, i32, i32, i64, i64, i64, ctypes.POINTER(TsvdOpts), vp, i64, vp, vp, i64,
                                ctypes.POINTER(TsvdInfo), vp]
     lib.tsvd_dense.restype = ctypes.c_int
+    lib.tsvd_dense_batched.argtypes = [vp, i32, ctypes.POINTER(TsvdProblem), i64, ctypes.POINTER(TsvdInfo),
+                                       ctypes.POINTER(ctypes.c_int32), vp]
+    lib.tsvd_dense_batched.restype = ctypes.c_int
+    lib.tsvd_server_create.argtypes = [vp, ctypes.POINTER(TsvdServerConfig), ctypes.POINTER(vp)]
+    lib.tsvd_server_create.restype = ctypes.c_int
+    lib.tsvd_server_submit.argtypes = [vp, ctypes.POINTER(TsvdProblem), i32, ctypes.POINTER(ctypes.c_uint64)]
+    lib.tsvd_server_submit.restype = ctypes.c_int
+    lib.tsvd_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(i32), ctypes.POINTER(TsvdInfo),
+                                     ctypes.POINTER(i32)]
+    lib.tsvd_server_poll.restype = ctypes.c_int
+    lib.tsvd_server_wait.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(TsvdInfo)]
+    lib.tsvd_server_wait.restype = ctypes.c_int
+    lib.tsvd_server_get_stats.argtypes = [vp, ctypes.POINTER(TsvdServerStats)]
+    lib.tsvd_server_get_stats.restype = ctypes.c_int
+    lib.tsvd_server_last_error.argtypes = [vp]
+    lib.tsvd_server_last_error.restype = ctypes.c_char_p
+    lib.tsvd_server_destroy.argtypes = [vp]
+    lib.tsvd_server_destroy.restype = None
     lib.tsvd_ctx_set_tuning.argtypes = [vp, ctypes.POINTER(TsvdTuning)]
     lib.tsvd_ctx_set_tuning.restype = ctypes.c_int
     lib.tsvd_ctx_get_tuning.argtypes = [vp, ctypes.POINTER(TsvdTuning)]
@@ -174,6 +239,7 @@ class Context:
             raise RuntimeError("no HIP device is visible: the t-SVD library runs on the GPU only")
         self.lib = load_library()
         self.device = device
+        self.num_cu = torch.cuda.get_device_properties(device).multi_processor_count
         h = ctypes.c_void_p()
         st = self.lib.tsvd_ctx_create(device, ctypes.byref(h))
         if st != OK:
@@ -206,16 +272,22 @@ class Context:
         return st
 
 
-def set_tuning(ctx: Context, gram_tile: int = 0, gram_chunks: int = 0, power_blocks: int = 0):
+TUNING_FIELDS = ("gram_tile", "gram_chunks", "power_blocks", "team_kib", "group_kchunk")
+
+
+def set_tuning(ctx: Context, gram_tile: int = 0, gram_chunks: int = 0, power_blocks: int = 0, team_kib: int = 0,
+               group_kchunk: int = 0):
     """Set the context's launch-shape tuning (0 = library choice)."""
-    t = TsvdTuning(int(gram_tile), int(gram_chunks), int(power_blocks), 0)
+    t = TsvdTuning()
+    t.gram_tile, t.gram_chunks, t.power_blocks = int(gram_tile), int(gram_chunks), int(power_blocks)
+    t.team_kib, t.group_kchunk = int(team_kib), int(group_kchunk)
     ctx.check(ctx.lib.tsvd_ctx_set_tuning(ctx.handle, ctypes.byref(t)))
 
 
 def get_tuning(ctx: Context) -> dict:
     t = TsvdTuning()
     ctx.check(ctx.lib.tsvd_ctx_get_tuning(ctx.handle, ctypes.byref(t)))
-    return {"gram_tile": t.gram_tile, "gram_chunks": t.gram_chunks, "power_blocks": t.power_blocks}
+    return {f: getattr(t, f) for f in TUNING_FIELDS}
 
 
 def _stream(stream):
@@ -280,6 +352,7 @@ def _info_dict(info: TsvdInfo, it, lam, k, status):
         "t_total_ms": info.t_total_ms,
         "workspace_bytes": info.workspace_bytes,
         "h2d_bytes": info.h2d_bytes,
+        "latency_ms": info.latency_ms,
     }
 
 
@@ -380,6 +453,158 @@ def tsvd_dense(ctx: Context, A, k, eps, v0, max_iter=10000, fixed_iters=None, gr
     ctx.check(st, allow=(OK,) if raise_not_converged else (OK, NOT_CONVERGED))
     del keep
     return U, S, V, _info_dict(info, it, lam, kk, st)
+
+
+def _fill_problem(ctx: Context, q: TsvdProblem, p: dict, dev, zero_outputs: bool = True):
+    """Fill a TsvdProblem from a problem dict; allocate U, S, V on `dev`
+    (uninitialised when zero_outputs is False: the library clears them on its
+    own stream, and a fill kernel on torch's stream would race with it)."""
+    torch = _torch()
+    A = p["A"]
+    m, n, lda = _rowmajor(A)
+    k = int(p["k"])
+    kk = min(m, n) if k == -1 else k
+    branch = int(p.get("branch", 0))
+    right = (m > n) if branch == 1 else (m >= n)
+    d = n if right else m
+    _check_v0(p["v0"], kk, d, dev)
+    if zero_outputs:
+        U = _colmajor_out(m, kk, dev)
+        V = _colmajor_out(n, kk, dev)
+        S = torch.zeros(kk, dtype=torch.float64, device=dev)
+    else:
+        U = torch.empty((kk, m), dtype=torch.float64, device=dev).T
+        V = torch.empty((kk, n), dtype=torch.float64, device=dev).T
+        S = torch.empty(kk, dtype=torch.float64, device=dev)
+    o, kp = _make_opts(ctx.lib, k, p["eps"], p["v0"], p.get("max_iter", 10000), p.get("fixed_iters"),
+                       p.get("gram", "auto"), 0, 0, branch)
+    it = (ctypes.c_int32 * kk)()
+    lam = (ctypes.c_double * kk)()
+    q.A = ctypes.c_void_p(A.data_ptr())
+    q.dtype = _dtype_code(A)
+    q.m, q.n, q.lda = m, n, lda
+    q.opts = o
+    q.U, q.ldu = ctypes.c_void_p(U.data_ptr()), U.stride(1)
+    q.S = ctypes.c_void_p(S.data_ptr())
+    q.V, q.ldv = ctypes.c_void_p(V.data_ptr()), V.stride(1)
+    return U, S, V, kk, it, lam, kp
+
+
+def tsvd_dense_batched(ctx: Context, problems, hbm_budget=0, stream=None, raise_errors=False):
+    """Many dense t-SVDs in one pass.  `problems` is a list of dicts with keys
+    A (float32 device tensor, row-major), k, eps, v0 and optionally max_iter,
+    fixed_iters, gram ("auto", "fp32", "bf16x3") and branch.  Returns a list of
+    (U, S, V, info) in the same order; info["status"] is each problem's
+    status.  raise_errors=True raises on the first failing problem."""
+    torch = _torch()
+    count = len(problems)
+    arr = (TsvdProblem * max(count, 1))()
+    infos = (TsvdInfo * max(count, 1))()
+    stats = (ctypes.c_int32 * max(count, 1))()
+    keep, outs = [], []
+    for i, p in enumerate(problems):
+        if not p["A"].is_cuda:
+            raise ValueError("batched problems take device tensors")
+        U, S, V, kk, it, lam, kp = _fill_problem(ctx, arr[i], p, p["A"].device)
+        infos[i].iters = ctypes.cast(it, ctypes.POINTER(ctypes.c_int32))
+        infos[i].lambda_ = ctypes.cast(lam, ctypes.POINTER(ctypes.c_double))
+        keep.append((kp, it, lam))
+        outs.append((U, S, V, kk, it, lam))
+    st = ctx.lib.tsvd_dense_batched(ctx.handle, count, arr, int(hbm_budget), infos, stats, _stream(stream))
+    if raise_errors:
+        ctx.check(st)
+    elif st not in (OK, NOT_CONVERGED) and count and all(stats[i] == OK for i in range(count)):
+        ctx.check(st)  # a failure before any problem ran (arguments, memory, HIP)
+    res = []
+    for i, (U, S, V, kk, it, lam) in enumerate(outs):
+        res.append((U, S, V, _info_dict(infos[i], it, lam, kk, stats[i])))
+    del keep
+    return res
+
+
+class Server:
+    """A tsvd_server: continuous batching of dense requests on the context's
+    device.  The context must not be used for other calls while the server
+    lives.  submit() returns a ticket at once; poll()/wait() return
+    (U, S, V, info) once the request completed (info["status"] holds its
+    status)."""
+
+    def __init__(self, ctx: Context, hbm_budget: int, max_slots: int = 0, max_batch: int = 0):
+        self.ctx = ctx
+        cfg = TsvdServerConfig(int(hbm_budget), int(max_slots), int(max_batch))
+        h = ctypes.c_void_p()
+        ctx.check(ctx.lib.tsvd_server_create(ctx.handle, ctypes.byref(cfg), ctypes.byref(h)))
+        self.handle = h
+        self._live = {}  # ticket -> (outputs, references kept alive)
+
+    def submit(self, problem: dict) -> int:
+        """Queue one request (keys as for tsvd_dense_batched).  A may be a
+        device tensor or a pinned host tensor (copied by the server)."""
+        torch = _torch()
+        A = problem["A"]
+        if A.is_cuda:
+            loc, dev = LOC_DEVICE, A.device
+        elif A.is_pinned():
+            loc, dev = LOC_PINNED_HOST, torch.device("cuda", self.ctx.device)
+        else:
+            raise ValueError("A must be a device tensor or a pinned host tensor")
+        q = TsvdProblem()
+        U, S, V, kk, it, lam, kp = _fill_problem(self.ctx, q, problem, dev, zero_outputs=False)
+        t = ctypes.c_uint64()
+        st = self.ctx.lib.tsvd_server_submit(self.handle, ctypes.byref(q), loc, ctypes.byref(t))
+        if st != OK:
+            raise TsvdError(st, self.ctx.lib.tsvd_server_last_error(self.handle).decode())
+        self._live[t.value] = ((U, S, V, kk, it, lam), (problem, kp))
+        return t.value
+
+    def _result(self, ticket, info, st):
+        (U, S, V, kk, it, lam), _ = self._live.pop(ticket)
+        return U, S, V, _info_dict(info, it, lam, kk, st)
+
+    def _info_for(self, ticket):
+        (_, _, _, _, it, lam), _ = self._live[ticket]
+        info = TsvdInfo()
+        info.iters = ctypes.cast(it, ctypes.POINTER(ctypes.c_int32))
+        info.lambda_ = ctypes.cast(lam, ctypes.POINTER(ctypes.c_double))
+        return info
+
+    def poll(self, ticket: int):
+        """None while the request runs, else (U, S, V, info)."""
+        info = self._info_for(ticket)
+        done, st = ctypes.c_int32(), ctypes.c_int32()
+        self.ctx.check(self.ctx.lib.tsvd_server_poll(self.handle, ticket, ctypes.byref(done), ctypes.byref(info),
+                                                     ctypes.byref(st)))
+        if not done.value:
+            return None
+        return self._result(ticket, info, st.value)
+
+    def wait(self, ticket: int):
+        info = self._info_for(ticket)
+        st = self.ctx.lib.tsvd_server_wait(self.handle, ticket, ctypes.byref(info))
+        return self._result(ticket, info, st)
+
+    def stats(self) -> dict:
+        s = TsvdServerStats()
+        self.ctx.check(self.ctx.lib.tsvd_server_get_stats(self.handle, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in TsvdServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.ctx.lib.tsvd_server_destroy(self.handle)
+            self.handle = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 class Csr:

@@ -12,6 +12,7 @@
 #include "../../include/tsvd.h"
 #include "common.h"
 
+#include "ctx.h"
 #include "internal.h"
 
 namespace tsvd {
@@ -29,19 +30,8 @@ int hip_fail(hipError_t e, const char* what, const char* file, int line) {
 
 using namespace tsvd;
 
-struct tsvd_ctx {
-  int device = 0;
-  int num_cu = 0;
-  size_t max_lds = 0;
-  std::string last_error;
-  void* ws = nullptr;
-  size_t ws_bytes = 0;
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-  hipStream_t copy_stream = nullptr;  // host->device batch copies (pinned-host input)
-  tsvd_tuning tuning = {0, 0, 0, 0};
-};
+namespace tsvd {
 
-namespace {
 
 tsvd_status fail(tsvd_ctx* ctx, tsvd_status st, const char* fmt, ...) {
   if (ctx) {
@@ -60,21 +50,6 @@ tsvd_status from_internal(tsvd_ctx* ctx, int rc, const char* where) {
   if (rc == TSVD_ERR_HIP) return fail(ctx, TSVD_ERR_HIP, "%s: %s", where, g_hip_msg.c_str());
   return fail(ctx, TSVD_ERR_INTERNAL, "%s: internal error %d", where, rc);
 }
-
-struct Bump {
-  char* base;
-  size_t off = 0;
-  size_t cap;
-  explicit Bump(void* b, size_t c) : base((char*)b), cap(c) {}
-  void* take(size_t bytes) {
-    off = (off + 255) & ~(size_t)255;
-    void* p = base + off;
-    off += bytes;
-    return p;
-  }
-};
-
-size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 tsvd_status ensure_ws(tsvd_ctx* ctx, size_t bytes, int64_t budget) {
   if (budget > 0 && (int64_t)bytes > budget)
@@ -117,7 +92,7 @@ tsvd_status check_mode(tsvd_ctx* ctx, int mode, int32_t dtype) {
 
 bool right_side(int64_t m, int64_t n, int32_t branch) { return branch == 1 ? (m > n) : (m >= n); }
 
-}  // namespace
+}  // namespace tsvd
 
 extern "C" {
 
@@ -146,6 +121,10 @@ tsvd_status tsvd_ctx_set_tuning(tsvd_ctx* ctx, const tsvd_tuning* t) {
   if (t->gram_chunks < 0 || t->gram_chunks > 4096) return fail(ctx, TSVD_ERR_INVALID_ARG, "gram_chunks out of range");
   if (t->power_blocks < 0 || t->power_blocks > ctx->num_cu)
     return fail(ctx, TSVD_ERR_INVALID_ARG, "power_blocks must be in [0, %d]", ctx->num_cu);
+  if (t->team_kib != 0 && (t->team_kib < 8 || t->team_kib > 65536))
+    return fail(ctx, TSVD_ERR_INVALID_ARG, "team_kib must be 0 or in [8, 65536]");
+  if (t->group_kchunk != 0 && (t->group_kchunk < 32 || t->group_kchunk > (1 << 20)))
+    return fail(ctx, TSVD_ERR_INVALID_ARG, "group_kchunk must be 0 or in [32, 2^20]");
   ctx->tuning = *t;
   return TSVD_OK;
 }
@@ -318,6 +297,7 @@ tsvd_status tsvd_power_gram(tsvd_ctx* ctx, void* B, int32_t dtype, int64_t d, in
     info->converged = hs[1];
     info->rank_deficient = hs[3];
     info->branch_right = 1;
+    info->latency_ms = 0;
     if (info->iters) memcpy(info->iters, hit.data(), (size_t)k * 4);
     if (info->lambda) memcpy(info->lambda, hl.data(), (size_t)k * 8);
   }
@@ -508,6 +488,7 @@ static tsvd_status dense_pinned(tsvd_ctx* ctx, const float* A, int64_t m, int64_
     hipEventElapsedTime(&t, ctx->ev[0], ctx->ev[3]); info->t_total_ms = t;
     info->workspace_bytes = (int64_t)need;
     info->h2d_bytes = (int64_t)(m * n * 4) * (kd > 0 ? 2 : 1);
+    info->latency_ms = 0;
   }
   if (!hs[1] && !o->fixed_iters && o->eps > 0)
     return fail(ctx, TSVD_ERR_NOT_CONVERGED, "some triplet reached max_iter");
@@ -618,6 +599,7 @@ tsvd_status tsvd_dense(tsvd_ctx* ctx, const void* A, int32_t dtype, int32_t loc,
     hipEventElapsedTime(&t, ctx->ev[0], ctx->ev[3]); info->t_total_ms = t;
     info->workspace_bytes = (int64_t)need;
     info->h2d_bytes = 0;
+    info->latency_ms = 0;
   }
   if (!hs[1] && !o->fixed_iters && o->eps > 0)
     return fail(ctx, TSVD_ERR_NOT_CONVERGED, "some triplet reached max_iter");
@@ -866,6 +848,7 @@ tsvd_status tsvd_sparse(tsvd_ctx* ctx, const tsvd_csr* c, const tsvd_opts* o, do
     hipEventElapsedTime(&t, ctx->ev[0], ctx->ev[3]); info->t_total_ms = t;
     info->workspace_bytes = (int64_t)need;
     info->h2d_bytes = 0;
+    info->latency_ms = 0;
   }
   if (!all_conv && !o->fixed_iters && o->eps > 0)
     return fail(ctx, TSVD_ERR_NOT_CONVERGED, "some triplet reached max_iter");

@@ -235,6 +235,7 @@ __global__ __launch_bounds__(256) void finish_grouped_scale_kernel(const FinishJ
   const int jb = find_fjob(jobs, njobs, blockIdx.x, 1);
   const FinishJob& j = jobs[jb];
   const int c = (int)(blockIdx.x - j.cbegin);
+  if (c >= *j.kdone) return;
   double* W = j.side == 0 ? j.U : j.V;
   const int64_t ldw = j.side == 0 ? j.ldu : j.ldv;
   const int64_t Mw = j.side == 0 ? j.m : j.n;

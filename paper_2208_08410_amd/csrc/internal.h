@@ -85,6 +85,11 @@ struct PowerPlan {
 enum { ERR_NONE = 0, ERR_SPIN = 1, ERR_NONFINITE = 2, ERR_BADSTART = 3 };
 int power_plan(int dtype_bytes, int d, int k, int num_cu, size_t max_lds, int max_blocks_hint, PowerPlan* p);
 int power_launch(int is_f64, const PowerPlan& p, PowerArgs a, hipStream_t stream);
+// batched launch (FP32 Grams): grid = total team workgroups (co-resident,
+// cooperative); zero_words of exchange memory at zero_base are cleared first
+int power_team_launch(const PowerArgs* d_probs, const int* d_order, const PowerTeam* d_teams,
+                      const int* d_team_of_block, int grid, size_t lds_bytes, uint64_t* zero_base, size_t zero_words,
+                      hipStream_t stream);
 
 // ---- finishing pass (finish.hip)
 // one problem of a grouped finishing pass (FP32 A); k = triplets found
@@ -98,6 +103,7 @@ struct FinishJob {
   int64_t ldv;
   double* S;
   double* ssq;           // nb * k
+  const int* kdone;      // device: triplets the power phase produced (columns to scale)
   int nb, pad;           // row tiles of the product
   int64_t ubegin;        // first workgroup in the product launch (nb * column blocks units)
   int64_t cbegin;        // first workgroup in the scale launch (k units)

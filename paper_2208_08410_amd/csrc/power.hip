@@ -387,9 +387,10 @@ __device__ __forceinline__ void store_regrows(const RegRows<BT, NV, RR>& R, BT* 
 }
 
 // One problem solved by a team of G workgroups (this one is member b).  The
-// exchange counters persist across problems solved by the same team.
+// exchange counters persist across problems solved by the same team.  Returns
+// the error code this workgroup met (ERR_NONE on success).
 template <typename BT, int NV, int RR>
-__device__ void solve_problem(const PowerArgs& a, int b, int G, unsigned char* smem, uint32_t& epoch, uint32_t& nx,
+__device__ int solve_problem(const PowerArgs& a, int b, int G, unsigned char* smem, uint32_t& epoch, uint32_t& nx,
                               uint32_t& np) {
   constexpr int VN = VecOf<BT>::N;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -604,6 +605,7 @@ __device__ void solve_problem(const PowerArgs& a, int b, int G, unsigned char* s
     a.status[3] = rankdef ? 1 : 0;
   }
   if (err != ERR_NONE && tid == 0) atomicMax(a.status + 2, err);
+  return err;
 }
 
 // Single problem: the whole grid is one team.
@@ -629,7 +631,10 @@ __global__ __launch_bounds__(256, 1) void power_team_kernel(const PowerArgs* pro
     PowerArgs a = probs[order[i]];
     a.xex = td.xex; a.pex = td.pex; a.vex = td.vex; a.wex = td.wex; a.kscr = td.kscr;
     a.pw = td.pw; a.xwords = td.xwords; a.vstride = td.vstride;
-    solve_problem<float, 0, 0>(a, b, td.size, smem, epoch, nx, np);
+    const int err = solve_problem<float, 0, 0>(a, b, td.size, smem, epoch, nx, np);
+    // a timed-out wait leaves this workgroup's exchange counters out of step
+    // with its team: stop here (the team's other members time out in turn)
+    if (err == ERR_SPIN) return;
     __syncthreads();
   }
 }
@@ -709,6 +714,24 @@ int power_launch(int is_f64, const PowerPlan& p, PowerArgs a, hipStream_t stream
   TSVD_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, p.lds_bytes));
   if (per_cu < 1) return -2;
   TSVD_HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(p.G), dim3(256), args, p.lds_bytes, stream));
+  return 0;
+}
+
+int power_team_launch(const PowerArgs* d_probs, const int* d_order, const PowerTeam* d_teams,
+                      const int* d_team_of_block, int grid, size_t lds_bytes, uint64_t* zero_base, size_t zero_words,
+                      hipStream_t stream) {
+  if (grid <= 0) return 0;
+  if (zero_words) {
+    hipLaunchKernelGGL(zero_words_kernel, dim3(256), dim3(256), 0, stream, zero_base, zero_words);
+    TSVD_HIP_TRY(hipGetLastError());
+  }
+  const void* fn = (const void*)power_team_kernel;
+  TSVD_HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
+  int per_cu = 0;
+  TSVD_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, lds_bytes));
+  if (per_cu < 1) return -2;
+  void* args[] = {(void*)&d_probs, (void*)&d_order, (void*)&d_teams, (void*)&d_team_of_block};
+  TSVD_HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(grid), dim3(256), args, lds_bytes, stream));
   return 0;
 }
 

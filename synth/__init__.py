@@ -147,6 +147,31 @@ def dense_known_torch(m: int, n: int, s: np.ndarray, seed: int, device, keep_fac
     return A, Uk, Vk
 
 
+def householder_known_torch(m: int, n: int, s: np.ndarray, seed: int, device, reflectors: int = 2):
+    """A = H_L [diag(s); 0] H_R with H_L (m x m) and H_R (n x n) products of
+    `reflectors` Householder reflections I - 2 w w^T, w uniform on the sphere:
+    exactly orthogonal factors in O(mn) work (no QR), so the singular values
+    are s.  Built in FP64 on the device, returned as FP32 [m, n]."""
+    import torch
+
+    d = min(m, n)
+    g = rng(seed, TAG_U)
+    X = torch.zeros((m, n), dtype=torch.float64, device=device)
+    idx = torch.arange(d, device=device)
+    X[idx, idx] = torch.as_tensor(np.asarray(s[:d], dtype=np.float64), device=device)
+    for _ in range(reflectors):
+        w = g.standard_normal(n)
+        w = torch.as_tensor(w / np.linalg.norm(w), device=device)
+        X.sub_(torch.outer(2.0 * (X @ w), w))
+    for _ in range(reflectors):
+        u = g.standard_normal(m)
+        u = torch.as_tensor(u / np.linalg.norm(u), device=device)
+        X.sub_(torch.outer(u, 2.0 * (u @ X)))
+    A = X.to(torch.float32)
+    del X
+    return A
+
+
 def gaussian_dense(m: int, n: int, seed: int, dtype=np.float32) -> np.ndarray:
     """i.i.d. N(0,1) m x n matrix."""
     return rng(seed, TAG_NOISE).standard_normal((m, n)).astype(dtype)

@@ -66,3 +66,62 @@ def test_no_gpu_fails_loudly(lib):
     assert lib.tsvd_ctx_create(0, ctypes.byref(h)) != 0
     with pytest.raises(RuntimeError):
         P.Context(0)
+
+
+LAYOUT_C = r"""
+#include <stddef.h>
+#include <stdio.h>
+#include "tsvd.h"
+#define F(T, f) printf("%s.%s %zu %zu\n", #T, #f, offsetof(T, f), sizeof(((T*)0)->f));
+#define Z(T) printf("%s.sizeof %zu 0\n", #T, sizeof(T));
+int main(void) {
+  F(tsvd_opts, k) F(tsvd_opts, eps) F(tsvd_opts, max_iter) F(tsvd_opts, fixed_iters) F(tsvd_opts, v0)
+  F(tsvd_opts, gram) F(tsvd_opts, rows_per_block) F(tsvd_opts, hbm_budget) F(tsvd_opts, branch)
+  F(tsvd_opts, queue_depth) Z(tsvd_opts)
+  F(tsvd_tuning, gram_tile) F(tsvd_tuning, gram_chunks) F(tsvd_tuning, power_blocks) F(tsvd_tuning, team_kib)
+  F(tsvd_tuning, group_kchunk) F(tsvd_tuning, reserved) Z(tsvd_tuning)
+  F(tsvd_info, k_done) F(tsvd_info, iters) F(tsvd_info, lambda) F(tsvd_info, t_gram_ms) F(tsvd_info, h2d_bytes) F(tsvd_info, latency_ms)
+  Z(tsvd_info)
+  F(tsvd_problem, A) F(tsvd_problem, dtype) F(tsvd_problem, m) F(tsvd_problem, lda) F(tsvd_problem, opts)
+  F(tsvd_problem, U) F(tsvd_problem, ldu) F(tsvd_problem, S) F(tsvd_problem, V) F(tsvd_problem, ldv)
+  Z(tsvd_problem)
+  F(tsvd_server_config, hbm_budget) F(tsvd_server_config, max_slots) F(tsvd_server_config, max_batch)
+  Z(tsvd_server_config)
+  F(tsvd_server_stats, submitted) F(tsvd_server_stats, batches) F(tsvd_server_stats, mean_batch)
+  F(tsvd_server_stats, p50_ms) F(tsvd_server_stats, max_ms) F(tsvd_server_stats, peak_bytes)
+  F(tsvd_server_stats, waiting) Z(tsvd_server_stats)
+  return 0;
+}
+"""
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The ctypes mirrors of the public structs have the C compiler's offsets
+    and sizes (host gcc on the same header)."""
+    import shutil
+    import subprocess
+    if not shutil.which("gcc"):
+        pytest.skip("gcc not available")
+    src = tmp_path / "layout.c"
+    src.write_text(LAYOUT_C)
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    mirrors = {"tsvd_opts": P.TsvdOpts, "tsvd_tuning": P.TsvdTuning, "tsvd_info": P.TsvdInfo,
+               "tsvd_problem": P.TsvdProblem, "tsvd_server_config": P.TsvdServerConfig,
+               "tsvd_server_stats": P.TsvdServerStats}
+    rename = {"lambda": "lambda_"}
+    checked = 0
+    for line in out:
+        if not line.strip():
+            continue
+        name, off, size = line.split()
+        sname, field = name.split(".")
+        cls = mirrors[sname]
+        if field == "sizeof":
+            assert ctypes.sizeof(cls) == int(off), sname
+        else:
+            desc = getattr(cls, rename.get(field, field))
+            assert (desc.offset, desc.size) == (int(off), int(size)), name
+        checked += 1
+    assert checked >= 40

@@ -107,4 +107,9 @@ def test_tuning_rejects_bad_values(ctx):
         P.set_tuning(ctx, gram_tile=64)
     with pytest.raises(P.TsvdError):
         P.set_tuning(ctx, power_blocks=100000)
-    assert P.get_tuning(ctx) == {"gram_tile": 0, "gram_chunks": 0, "power_blocks": 0}
+    with pytest.raises(P.TsvdError):
+        P.set_tuning(ctx, team_kib=4)
+    with pytest.raises(P.TsvdError):
+        P.set_tuning(ctx, group_kchunk=16)
+    assert P.get_tuning(ctx) == {"gram_tile": 0, "gram_chunks": 0, "power_blocks": 0, "team_kib": 0,
+                                 "group_kchunk": 0}
