@@ -12,58 +12,99 @@ namespace tsvd {
 
 constexpr int FBM = 128;  // output rows per workgroup
 constexpr int FBN = 64;   // output columns per workgroup
-constexpr int FBK = 16;   // contraction per stage
-constexpr int FLDK = FBK + 2;
-
-__device__ __forceinline__ int kpos4(int k) { return (k & 3) * 4 + (k >> 2); }
+constexpr int FBK = 32;   // contraction per stage (8 MFMA k-steps)
+constexpr int FLDA = FBK + 1;  // LDS row of A (elements): odd stride spreads rows over banks
+constexpr int FLDX = FBK + 1;  // LDS row of X (doubles)
 
 // W[M x N] (column-major, ldw) = op(A) X, X is K x N column-major (ldx).
 // side 0: op(A) = A (M = m, K = n); side 1: op(A) = A^T (M = n, K = m).
+// A tile (128 x 32) and X tile (32 x 64) are staged through LDS, the next
+// stage's loads in flight (16-byte loads when vec) while this stage's 64
+// v_mfma_f64_16x16x4f64 per wave run.  A is converted to FP64 on the way to
+// the MFMA, so each product a_ik x_kj is exact and only the accumulation rounds.
 template <typename AT, int SIDE>
 __device__ __forceinline__ void finish_gemm_unit(const AT* A, int64_t lda, int64_t M, int64_t K, const double* X,
                                                  int64_t ldx, int N, double* W, int64_t ldw, double* ssq, int bx,
-                                                 int by) {
-  __shared__ double As[2][FBM * FLDK];
-  __shared__ double Xs[2][FBN * FLDK];
+                                                 int by, bool vec) {
+  __shared__ AT As[2][FBM * FLDA];
+  __shared__ double Xs[2][FBN * FLDX];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t m0 = (int64_t)bx * FBM;
   const int j0 = by * FBN;
   const int nk = (int)((K + FBK - 1) / FBK);
+  constexpr int VA = sizeof(AT) == 4 ? 4 : 2;     // elements per 16-byte load of A
+  constexpr int NA = FBM * FBK / VA / 256;        // A vectors per thread per stage (4 or 8)
+  constexpr int NX = FBN * FBK / 2 / 256;         // X double2 per thread per stage (4)
 
-  double av[8], xv[4];
+  AT av[NA][VA];
+  double xv[NX][2];
+  // A vector f: side 0 -> row r = f / (FBK/VA), k = (f % (FBK/VA)) * VA (k-contiguous in A)
+  //             side 1 -> k = f / (FBM/VA), r = (f % (FBM/VA)) * VA (r-contiguous in A)
   auto load = [&](int kt) {
     const int64_t k0 = (int64_t)kt * FBK;
 #pragma unroll
-    for (int e = 0; e < 8; e++) {
+    for (int e = 0; e < NA; e++) {
       const int f = tid + 256 * e;
       int r, kk;
-      if (SIDE == 0) { kk = f % FBK; r = f / FBK; }
-      else { r = f % FBM; kk = f / FBM; }
+      if (SIDE == 0) { r = f / (FBK / VA); kk = (f % (FBK / VA)) * VA; }
+      else { kk = f / (FBM / VA); r = (f % (FBM / VA)) * VA; }
       const int64_t gr = m0 + r, gk = k0 + kk;
-      av[e] = (gr < M && gk < K) ? (double)(SIDE == 0 ? A[gr * lda + gk] : A[gk * lda + gr]) : 0.0;
+      if (SIDE == 0) {
+        const AT* p = A + gr * lda + gk;
+        if (vec && gr < M && gk + VA <= K) {
+          if constexpr (VA == 4) { const float4 t = *(const float4*)p; av[e][0] = t.x; av[e][1] = t.y; av[e][2] = t.z; av[e][3] = t.w; }
+          else { const double2 t = *(const double2*)p; av[e][0] = t.x; av[e][1] = t.y; }
+        } else {
+#pragma unroll
+          for (int u = 0; u < VA; u++) av[e][u] = (gr < M && gk + u < K) ? p[u] : (AT)0;
+        }
+      } else {
+        const AT* p = A + gk * lda + gr;
+        if (vec && gk < K && gr + VA <= M) {
+          if constexpr (VA == 4) { const float4 t = *(const float4*)p; av[e][0] = t.x; av[e][1] = t.y; av[e][2] = t.z; av[e][3] = t.w; }
+          else { const double2 t = *(const double2*)p; av[e][0] = t.x; av[e][1] = t.y; }
+        } else {
+#pragma unroll
+          for (int u = 0; u < VA; u++) av[e][u] = (gk < K && gr + u < M) ? p[u] : (AT)0;
+        }
+      }
     }
 #pragma unroll
-    for (int e = 0; e < 4; e++) {
+    for (int e = 0; e < NX; e++) {
       const int f = tid + 256 * e;
-      const int kk = f % FBK, j = f / FBK;
+      const int j = f / (FBK / 2), kk = (f % (FBK / 2)) * 2;
       const int64_t gk = k0 + kk;
-      xv[e] = (gk < K && j0 + j < N) ? X[(int64_t)(j0 + j) * ldx + gk] : 0.0;
+      const double* p = X + (int64_t)(j0 + j) * ldx + gk;
+      const bool colok = j0 + j < N;
+      if (colok && gk + 2 <= K && (((uintptr_t)p & 15) == 0)) {
+        const double2 t = *(const double2*)p;
+        xv[e][0] = t.x; xv[e][1] = t.y;
+      } else {
+        xv[e][0] = (colok && gk < K) ? p[0] : 0.0;
+        xv[e][1] = (colok && gk + 1 < K) ? p[1] : 0.0;
+      }
     }
   };
   auto store = [&](int buf) {
 #pragma unroll
-    for (int e = 0; e < 8; e++) {
+    for (int e = 0; e < NA; e++) {
       const int f = tid + 256 * e;
-      int r, kk;
-      if (SIDE == 0) { kk = f % FBK; r = f / FBK; }
-      else { r = f % FBM; kk = f / FBM; }
-      As[buf][r * FLDK + kpos4(kk)] = av[e];
+      if (SIDE == 0) {
+        const int r = f / (FBK / VA), kk = (f % (FBK / VA)) * VA;
+#pragma unroll
+        for (int u = 0; u < VA; u++) As[buf][r * FLDA + kk + u] = av[e][u];
+      } else {
+        const int kk = f / (FBM / VA), r = (f % (FBM / VA)) * VA;
+#pragma unroll
+        for (int u = 0; u < VA; u++) As[buf][(r + u) * FLDA + kk] = av[e][u];
+      }
     }
 #pragma unroll
-    for (int e = 0; e < 4; e++) {
+    for (int e = 0; e < NX; e++) {
       const int f = tid + 256 * e;
-      const int kk = f % FBK, j = f / FBK;
-      Xs[buf][j * FLDK + kpos4(kk)] = xv[e];
+      const int j = f / (FBK / 2), kk = (f % (FBK / 2)) * 2;
+      Xs[buf][j * FLDX + kk] = xv[e][0];
+      Xs[buf][j * FLDX + kk + 1] = xv[e][1];
     }
   };
 
@@ -77,18 +118,18 @@ __device__ __forceinline__ void finish_gemm_unit(const AT* A, int64_t lda, int64
 
   if (nk > 0) { load(0); store(0); }
   __syncthreads();
-  const int q = lane >> 4;
+  const int q = lane >> 4, l16 = lane & 15;
   for (int kt = 0; kt < nk; kt++) {
     const int cur = kt & 1;
     const bool more = kt + 1 < nk;
     if (more) load(kt + 1);
 #pragma unroll
-    for (int s = 0; s < 4; s++) {
+    for (int t = 0; t < FBK / 4; t++) {
       double a[2], x[4];
 #pragma unroll
-      for (int i = 0; i < 2; i++) a[i] = As[cur][(wave * 32 + i * 16 + (lane & 15)) * FLDK + q * 4 + s];
+      for (int i = 0; i < 2; i++) a[i] = (double)As[cur][(wave * 32 + i * 16 + l16) * FLDA + 4 * t + q];
 #pragma unroll
-      for (int j = 0; j < 4; j++) x[j] = Xs[cur][(j * 16 + (lane & 15)) * FLDK + q * 4 + s];
+      for (int j = 0; j < 4; j++) x[j] = Xs[cur][(j * 16 + l16) * FLDX + 4 * t + q];
 #pragma unroll
       for (int i = 0; i < 2; i++)
 #pragma unroll
@@ -132,8 +173,8 @@ __device__ __forceinline__ void finish_gemm_unit(const AT* A, int64_t lda, int64
 template <typename AT, int SIDE>
 __global__ __launch_bounds__(256) void finish_gemm_kernel(const AT* A, int64_t lda, int64_t M, int64_t K,
                                                           const double* X, int64_t ldx, int N, double* W,
-                                                          int64_t ldw, double* ssq) {
-  finish_gemm_unit<AT, SIDE>(A, lda, M, K, X, ldx, N, W, ldw, ssq, blockIdx.x, blockIdx.y);
+                                                          int64_t ldw, double* ssq, int vec) {
+  finish_gemm_unit<AT, SIDE>(A, lda, M, K, X, ldx, N, W, ldw, ssq, blockIdx.x, blockIdx.y, vec != 0);
 }
 
 // sigma_j = sqrt(sum over row tiles of ssq[b][j]), added in tile order.
@@ -219,7 +260,8 @@ __global__ __launch_bounds__(256) void finish_grouped_gemm_kernel(const FinishJo
   const int64_t ldx = SIDE == 0 ? j.ldv : j.ldu;
   double* W = SIDE == 0 ? j.U : j.V;
   const int64_t ldw = SIDE == 0 ? j.ldu : j.ldv;
-  finish_gemm_unit<float, SIDE>((const float*)j.A, j.lda, M, K, X, ldx, j.k, W, ldw, j.ssq, u % j.nb, u / j.nb);
+  const bool vec = (((uintptr_t)j.A & 15) == 0) && (j.lda % 4 == 0);
+  finish_gemm_unit<float, SIDE>((const float*)j.A, j.lda, M, K, X, ldx, j.k, W, ldw, j.ssq, u % j.nb, u / j.nb, vec);
 }
 
 __global__ void finish_grouped_sigma_kernel(const FinishJob* jobs) {
@@ -266,20 +308,21 @@ int finish_gemm_launch(int is_f64, int side, const void* A, int64_t m, int64_t n
   const int64_t K = side == 0 ? n : m;
   const int64_t nb = (M + FBM - 1) / FBM;
   dim3 grid((unsigned)nb, (unsigned)((k + FBN - 1) / FBN));
+  const int vec = (((uintptr_t)A & 15) == 0) && (lda % (is_f64 ? 2 : 4) == 0);
   if (is_f64) {
     if (side == 0)
       hipLaunchKernelGGL((finish_gemm_kernel<double, 0>), grid, dim3(256), 0, stream, (const double*)A, lda, M, K, X,
-                         ldx, k, W, ldw, ssq);
+                         ldx, k, W, ldw, ssq, vec);
     else
       hipLaunchKernelGGL((finish_gemm_kernel<double, 1>), grid, dim3(256), 0, stream, (const double*)A, lda, M, K, X,
-                         ldx, k, W, ldw, ssq);
+                         ldx, k, W, ldw, ssq, vec);
   } else {
     if (side == 0)
       hipLaunchKernelGGL((finish_gemm_kernel<float, 0>), grid, dim3(256), 0, stream, (const float*)A, lda, M, K, X,
-                         ldx, k, W, ldw, ssq);
+                         ldx, k, W, ldw, ssq, vec);
     else
       hipLaunchKernelGGL((finish_gemm_kernel<float, 1>), grid, dim3(256), 0, stream, (const float*)A, lda, M, K, X,
-                         ldx, k, W, ldw, ssq);
+                         ldx, k, W, ldw, ssq, vec);
   }
   TSVD_HIP_TRY(hipGetLastError());
   return 0;

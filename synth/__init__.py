@@ -229,6 +229,58 @@ def spiked_rows(m: int, n: int, rank: int, seed: int, row0: int, rows: int,
     return out
 
 
+def spiked_rows_torch(m: int, n: int, rank: int, seed: int, row0: int, rows: int, device,
+                      strength: float = 50.0, decay: float = 0.9, yfac=None):
+    """Rows [row0, row0+rows) of the same spiked recipe, generated on a torch
+    device (torch's random stream, seeded per 2^14-row block, so any row range
+    is reproducible): A = G + sum_j theta_j x_j y_j^T with G, x i.i.d. N(0, 1)
+    (x scaled by 1/sqrt(m)), y the Haar factor of ``spiked_factors`` (pass it
+    as ``yfac`` on the device to skip its QR).  FP32."""
+    import torch
+
+    if yfac is None:
+        y, _ = spiked_factors(m, n, rank, seed, strength, decay)
+        yfac = torch.as_tensor(y, device=device)
+    theta = torch.as_tensor(strength * math.sqrt(m) * decay ** np.arange(rank, dtype=np.float64), device=device)
+    gen = torch.Generator(device=device)
+    block = 1 << 14
+    out = torch.empty((rows, n), dtype=torch.float32, device=device)
+    r = row0
+    while r < row0 + rows:
+        b = r // block
+        off = r - b * block
+        take = min(block - off, row0 + rows - r)
+        gen.manual_seed((int(seed) * 1000003 + TAG_NOISE * 7919 + b) & 0x7FFFFFFFFFFFFFFF)
+        g = torch.randn((block, n), generator=gen, dtype=torch.float32, device=device)[off:off + take]
+        gen.manual_seed((int(seed) * 1000003 + TAG_SPIKE_X * 7919 + b) & 0x7FFFFFFFFFFFFFFF)
+        x = torch.randn((block, rank), generator=gen, dtype=torch.float64, device=device)[off:off + take]
+        x = x / math.sqrt(m)
+        out[r - row0:r - row0 + take] = g + ((x * theta) @ yfac.T).to(torch.float32)
+        r += take
+    return out
+
+
+def csr_uniform_torch(m: int, n: int, density: float, seed: int, device):
+    """CSR on a torch device with the recipe of ``csr_uniform`` except that the
+    columns of a row are uniform draws kept in draw order (not sorted; a
+    repeated column, probability ~(density n)^2 / 2n per row, stays a repeated
+    entry): row lengths Poisson(density * n), values N(0, 1) FP32, int64 row
+    pointers, int32 columns.  For sizes too large for the host generator."""
+    import torch
+
+    gen = torch.Generator(device=device)
+    gen.manual_seed((int(seed) * 1000003 + TAG_CSR) & 0x7FFFFFFFFFFFFFFF)
+    lam = torch.full((m,), float(density) * n, dtype=torch.float32, device=device)
+    counts = torch.poisson(lam, generator=gen).to(torch.int64)
+    rowptr = torch.zeros(m + 1, dtype=torch.int64, device=device)
+    torch.cumsum(counts, 0, out=rowptr[1:])
+    del counts, lam
+    nnz = int(rowptr[-1])
+    col = torch.randint(0, n, (nnz,), generator=gen, dtype=torch.int32, device=device)
+    val = torch.randn(nnz, generator=gen, dtype=torch.float32, device=device)
+    return rowptr, col, val
+
+
 # --- sparse CSR -----------------------------------------------------------------
 
 def csr_uniform(m: int, n: int, density: float, seed: int):

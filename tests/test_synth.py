@@ -41,3 +41,25 @@ def test_request_stream_shapes_and_rate():
     assert {r.k for r in reqs} <= {8, 16, 32, 64}
     # log-uniform: the median of log m sits mid-range
     assert abs(np.median(np.log(ms)) - (np.log(1024) + np.log(65536)) / 2) < 0.15
+
+
+def test_spiked_rows_torch_row_ranges_and_spikes():
+    torch = pytest.importorskip("torch")
+    a = synth.spiked_rows_torch(20000, 48, 3, 1, 0, 20000, "cpu")
+    b = synth.spiked_rows_torch(20000, 48, 3, 1, 16380, 10, "cpu")  # crosses a 2^14-row block edge
+    assert torch.equal(a[16380:16390], b)
+    sv = np.linalg.svd(a.double().numpy(), compute_uv=False)
+    theta = 50 * np.sqrt(20000) * 0.9 ** np.arange(3)
+    # spikes far above the noise bulk (~sqrt(m) + sqrt(n)); x is orthonormal to O(1/sqrt(m))
+    assert np.all(np.abs(sv[:3] - theta) / theta < 0.05) and sv[3] < 2 * (np.sqrt(20000) + np.sqrt(48))
+
+
+def test_csr_uniform_torch_is_valid_csr():
+    torch = pytest.importorskip("torch")
+    rp, col, val = synth.csr_uniform_torch(3000, 7000, 0.002, 4, "cpu")
+    assert rp.dtype == torch.int64 and col.dtype == torch.int32 and val.dtype == torch.float32
+    assert int(rp[0]) == 0 and bool(torch.all(rp[1:] >= rp[:-1])) and int(rp[-1]) == col.numel() == val.numel()
+    assert int(col.min()) >= 0 and int(col.max()) < 7000
+    assert abs(col.numel() / (3000 * 7000 * 0.002) - 1) < 0.05
+    rp2, col2, _ = synth.csr_uniform_torch(3000, 7000, 0.002, 4, "cpu")
+    assert torch.equal(rp, rp2) and torch.equal(col, col2)
