@@ -54,7 +54,7 @@ def parse():
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--workload", default="dense", choices=["dense", "serve", "stream", "sparse"])
-    ap.add_argument("--stream-m", type=int, default=4_000_000, help="stream: rows of the pinned-host A")
+    ap.add_argument("--stream-m", type=int, default=2_000_000, help="stream: rows of the pinned-host A")
     ap.add_argument("--stream-n", type=int, default=8192)
     ap.add_argument("--stream-k", type=int, default=32)
     ap.add_argument("--batch-gb", type=float, default=4.0, help="stream: bytes of A per streamed row batch")
@@ -69,6 +69,8 @@ def parse():
     ap.add_argument("--pool-loc", default="host", choices=["host", "device"],
                     help="serve: pool in pinned host memory (copied per request) or in HBM")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serve: server device budget")
+    ap.add_argument("--team-kib", type=int, default=0, help="serve: batched power team size rule (0 = library)")
+    ap.add_argument("--max-batch", type=int, default=0, help="serve: requests per batch launch at most (0 = all)")
     return ap.parse_args()
 
 
@@ -166,6 +168,17 @@ def serve_cpu_baseline(shapes, ks, eps, seed):
     }
 
 
+def _batch_phases(results):
+    """Mean device time per batch phase (every request of a batch reports the
+    same batch phase times)."""
+    seen = {(x[1]["t_gram_ms"], x[1]["t_eig_ms"], x[1]["t_final_ms"], x[1]["t_total_ms"]) for x in results}
+    if not seen:
+        return {}
+    n = len(seen)
+    return {"gram": sum(t[0] for t in seen) / n, "power": sum(t[1] for t in seen) / n,
+            "finish": sum(t[2] for t in seen) / n, "total": sum(t[3] for t in seen) / n, "batches_seen": n}
+
+
 def serve_main(a):
     """Serving workload: Poisson arrivals into the library's request server."""
     import numpy as np
@@ -204,7 +217,9 @@ def serve_main(a):
     kch = synth.rng(a.seed, 78).choice([8, 16, 32, 64], size=len(arrivals))
     pick = synth.rng(a.seed, 79).integers(0, a.pool, size=len(arrivals))
     ctx = P.Context(0)
-    srv = P.Server(ctx, hbm_budget=int(a.budget_gb * (1 << 30)))
+    if a.team_kib:
+        P.set_tuning(ctx, team_kib=a.team_kib)
+    srv = P.Server(ctx, hbm_budget=int(a.budget_gb * (1 << 30)), max_batch=a.max_batch)
     tickets = []
     progress(f"serving {len(arrivals)} arrivals")
     t_start = time.perf_counter()
@@ -248,7 +263,8 @@ def serve_main(a):
                                f"m log-uniform [1024, 65536], n [128, 4096], k in {{8,16,32,64}}, s_i = 0.95^i, "
                                f"pool of {a.pool} matrices in {'pinned host memory' if a.pool_loc == 'host' else 'HBM'}"
                                f", eps={eps}", "rate": a.rate, "window_s": a.window, "pool": a.pool,
-                   "pool_loc": a.pool_loc, "budget_gb": a.budget_gb},
+                   "pool_loc": a.pool_loc, "budget_gb": a.budget_gb, "team_kib": a.team_kib,
+                   "max_batch": a.max_batch},
         "p50_ms": float(np.percentile(lat, 50)),
         "p99_ms": float(np.percentile(lat, 99)),
         "max_ms": float(lat.max()),
@@ -260,6 +276,7 @@ def serve_main(a):
         "meets_1e-6": bool(errs.max() < 1e-6),
         "batches": st["batches"],
         "mean_batch": st["mean_batch"],
+        "batch_phase_ms_mean": _batch_phases(results),
         "peak_bytes": st["peak_bytes"],
         "gen_seconds": gen_s,
     }
@@ -411,7 +428,9 @@ def sparse_main(a):
             e1.record()
             e1.synchronize()
             best = min(best, e0.elapsed_time(e1))
-        alg = nnz * (4 + 4 + 4) + (n + 1) * 8 + n * 8  # idx + val + gathered x, pointers, y
+        # algorithmic bytes of one product: index + value per nonzero, row
+        # pointers, x read once, y written once
+        alg = nnz * (4 + 4) + (n + 1) * 8 + n * 4 + n * 8
         rates["csr" if trans == 0 else "csc"] = {"ms": best, "gbs": alg / (best * 1e-3) / 1e9}
     g = torch.Generator(device=dev)
     g.manual_seed(a.seed)
@@ -426,7 +445,7 @@ def sparse_main(a):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t1
     per_iter = dt * 1e3 / (k * a.sparse_iters)
-    pair = nnz * 12 * 2 + 2 * ((n + 1) * 8 + n * 8)
+    pair = 2 * (nnz * 8 + (n + 1) * 8 + n * 4 + n * 8)
     out = {
         "metric": METRIC,
         "value": pair / (per_iter * 1e-3) / 1e9,
@@ -439,7 +458,7 @@ def sparse_main(a):
                                f"columns, N(0,1) values; k={k}, {a.sparse_iters} fixed iterations per triplet",
                    "n": n, "nnz": nnz, "k": k},
         "roofline": {"bound": "hbm", "achieved": rates["csr"]["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": rates["csr"]["gbs"] / HBM_PEAK_GBS, "traffic": None, "kernel": "spmv_kernel (CSR)"},
+                     "frac": rates["csr"]["gbs"] / HBM_PEAK_GBS, "traffic": None, "kernel": "spmv_tiles_kernel (A x)"},
         "spmv": rates,
         "ms_per_iteration": per_iter,
         "csc_build_ms": csc_ms,

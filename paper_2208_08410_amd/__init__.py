@@ -88,7 +88,9 @@ class TsvdTuning(ctypes.Structure):
         ("power_blocks", ctypes.c_int32),
         ("team_kib", ctypes.c_int32),
         ("group_kchunk", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 3),
+        ("sparse_row_bits", ctypes.c_int32),
+        ("sparse_col_bits", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -272,15 +274,17 @@ class Context:
         return st
 
 
-TUNING_FIELDS = ("gram_tile", "gram_chunks", "power_blocks", "team_kib", "group_kchunk")
+TUNING_FIELDS = ("gram_tile", "gram_chunks", "power_blocks", "team_kib", "group_kchunk", "sparse_row_bits",
+                 "sparse_col_bits")
 
 
 def set_tuning(ctx: Context, gram_tile: int = 0, gram_chunks: int = 0, power_blocks: int = 0, team_kib: int = 0,
-               group_kchunk: int = 0):
+               group_kchunk: int = 0, sparse_row_bits: int = 0, sparse_col_bits: int = 0):
     """Set the context's launch-shape tuning (0 = library choice)."""
     t = TsvdTuning()
     t.gram_tile, t.gram_chunks, t.power_blocks = int(gram_tile), int(gram_chunks), int(power_blocks)
     t.team_kib, t.group_kchunk = int(team_kib), int(group_kchunk)
+    t.sparse_row_bits, t.sparse_col_bits = int(sparse_row_bits), int(sparse_col_bits)
     ctx.check(ctx.lib.tsvd_ctx_set_tuning(ctx.handle, ctypes.byref(t)))
 
 

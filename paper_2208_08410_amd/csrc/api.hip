@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -121,6 +122,9 @@ tsvd_status tsvd_ctx_set_tuning(tsvd_ctx* ctx, const tsvd_tuning* t) {
   if (t->gram_chunks < 0 || t->gram_chunks > 4096) return fail(ctx, TSVD_ERR_INVALID_ARG, "gram_chunks out of range");
   if (t->power_blocks < 0 || t->power_blocks > ctx->num_cu)
     return fail(ctx, TSVD_ERR_INVALID_ARG, "power_blocks must be in [0, %d]", ctx->num_cu);
+  if (t->sparse_row_bits < 0 || t->sparse_row_bits > 13 || t->sparse_col_bits < 0 || t->sparse_col_bits > 31 ||
+      t->sparse_row_bits + t->sparse_col_bits > 32)
+    return fail(ctx, TSVD_ERR_INVALID_ARG, "sparse tile bits out of range (rows <= 13, rows + cols <= 32)");
   if (t->team_kib != 0 && (t->team_kib < 8 || t->team_kib > 65536))
     return fail(ctx, TSVD_ERR_INVALID_ARG, "team_kib must be 0 or in [8, 65536]");
   if (t->group_kchunk != 0 && (t->group_kchunk < 32 || t->group_kchunk > (1 << 20)))
@@ -325,7 +329,8 @@ tsvd_status tsvd_finish_dense(tsvd_ctx* ctx, const void* A, int32_t dtype, int64
   int rc = finish_launch(dtype == TSVD_F64, side, A, m, n, lda, X, ldx, k, W, ldw, S, (double*)ctx->ws,
                          (hipStream_t)stream);
   if (rc) return from_internal(ctx, rc, "finish");
-  rc = finish_scale_sign_launch(W, ldw, M, S, nullptr, 0, 0, nullptr, 0, 0, k, 0, (hipStream_t)stream);
+  rc = finish_scale_sign_launch(W, ldw, M, S, nullptr, 0, 0, nullptr, 0, 0, k, 0,
+                                (double*)ctx->ws + finish_tiles(m, n, side) * k, (hipStream_t)stream);
   return from_internal(ctx, rc, "finish scale");
 }
 
@@ -371,7 +376,7 @@ static tsvd_status dense_pinned(tsvd_ctx* ctx, const float* A, int64_t m, int64_
   const int64_t tiles_total = (m + 127) / 128 + nbatch;  // finish row tiles, one partial tile per batch at most
   const size_t buf_bytes = align256((size_t)R * n * 4);
   const size_t b_bytes = align256((size_t)d * ldb * 4);
-  const size_t ssq_bytes = align256((size_t)tiles_total * k * 8);
+  const size_t ssq_bytes = align256((size_t)(tiles_total + 2) * k * 8);
   const size_t need = (size_t)Q * buf_bytes + b_bytes + align256(part_bytes) + power_ws_bytes(pp, k) + ssq_bytes + 4096;
   tsvd_status st = ensure_ws(ctx, need, o->hbm_budget);
   if (st) return st;
@@ -464,7 +469,7 @@ static tsvd_status dense_pinned(tsvd_ctx* ctx, const float* A, int64_t m, int64_
     if (hipEventRecord(consumed[slot], s) != hipSuccess) { rc = TSVD_ERR_HIP; break; }
   }
   if (!rc && kd > 0) rc = finish_sigma_launch(ssq, tile_off, kd, S, s);
-  if (!rc && kd > 0) rc = finish_scale_sign_launch(U, ldu, m, S, V, ldv, n, U, ldu, m, kd, 1, s);
+  if (!rc && kd > 0) rc = finish_scale_sign_launch(U, ldu, m, S, V, ldv, n, U, ldu, m, kd, 1, ssq + tiles_total * k, s);
   hipEventRecord(ctx->ev[3], s);
   if (!rc && (hipStreamSynchronize(s) != hipSuccess || hipStreamSynchronize(cs) != hipSuccess)) rc = TSVD_ERR_HIP;
   cleanup();
@@ -575,7 +580,8 @@ tsvd_status tsvd_dense(tsvd_ctx* ctx, const void* A, int32_t dtype, int32_t loc,
   if (kd > 0) {
     rc = finish_launch(is_f64, side, A, m, n, lda, X, ldx, kd, W, ldw, S, ssq, stream);
     if (rc) return from_internal(ctx, rc, "finish");
-    rc = finish_scale_sign_launch(W, ldw, Mw, S, V, ldv, n, U, ldu, m, kd, 1, stream);
+    rc = finish_scale_sign_launch(W, ldw, Mw, S, V, ldv, n, U, ldu, m, kd, 1, ssq + finish_tiles(m, n, side) * k,
+                                  stream);
     if (rc) return from_internal(ctx, rc, "finish scale/sign");
   }
   hipEventRecord(ctx->ev[3], stream);
@@ -620,7 +626,20 @@ struct tsvd_csr {
   int64_t* colptr = nullptr;  // owned CSC copy
   int32_t* rowidx = nullptr;
   float* cval = nullptr;
+  // owned sliced tiles of A (from the CSR) and of A^T (from the CSC): dir 0 / 1
+  tsvd::TilePlan tp[2] = {};
+  int64_t* tptr[2] = {nullptr, nullptr};
+  uint32_t* tkey[2] = {nullptr, nullptr};
+  float* tval[2] = {nullptr, nullptr};
 };
+
+namespace {
+// y = A x (dir 0) or A^T x (dir 1) through the sliced tiles
+int csr_product(const tsvd_csr* c, int dir, const void* x, int x_is_f64, double* y, float* yf, hipStream_t s) {
+  return spmv_tiles_launch(c->tp[dir], c->tptr[dir], c->tkey[dir], c->tval[dir], dir == 0 ? c->m : c->n, x, x_is_f64,
+                           y, yf, s);
+}
+}  // namespace
 
 extern "C" {
 
@@ -667,6 +686,34 @@ tsvd_status tsvd_csr_create(tsvd_ctx* ctx, int64_t m, int64_t n, int64_t nnz, co
     tsvd_csr_destroy(c);
     return from_internal(ctx, rc, "CSC build");
   }
+  // sliced tiles for both products: A from the CSR, A^T from the CSC
+  for (int dir = 0; dir < 2; dir++) {
+    const int64_t rows = dir == 0 ? m : n, cols = dir == 0 ? n : m;
+    if (tiles_plan(rows, cols, ctx->num_cu, ctx->tuning.sparse_row_bits, ctx->tuning.sparse_col_bits, &c->tp[dir])) {
+      tsvd_csr_destroy(c);
+      return fail(ctx, TSVD_ERR_INVALID_ARG, "sparse tile bits out of range");
+    }
+    const int64_t nt = c->tp[dir].nchunks * c->tp[dir].nslices;
+    void* tscr = nullptr;
+    if (hipMalloc(&c->tptr[dir], (size_t)(nt + 1) * 8) != hipSuccess ||
+        hipMalloc(&c->tkey[dir], (size_t)(nnz > 0 ? nnz : 1) * 4) != hipSuccess ||
+        hipMalloc(&c->tval[dir], (size_t)(nnz > 0 ? nnz : 1) * 4) != hipSuccess ||
+        hipMalloc(&tscr, tiles_scratch_bytes(c->tp[dir])) != hipSuccess) {
+      (void)hipGetLastError();
+      hipFree(tscr);
+      tsvd_csr_destroy(c);
+      return fail(ctx, TSVD_ERR_OUT_OF_MEMORY, "allocating the sparse tiles (%lld nonzeros)", (long long)nnz);
+    }
+    rc = dir == 0 ? tiles_build(rowptr, col, val, m, nnz, c->tp[0], c->tptr[0], c->tkey[0], c->tval[0], tscr, s)
+                  : tiles_build(c->colptr, c->rowidx, c->cval, n, nnz, c->tp[1], c->tptr[1], c->tkey[1], c->tval[1],
+                                tscr, s);
+    if (rc == 0 && hipStreamSynchronize(s) != hipSuccess) rc = TSVD_ERR_HIP;
+    hipFree(tscr);
+    if (rc) {
+      tsvd_csr_destroy(c);
+      return from_internal(ctx, rc, "tile build");
+    }
+  }
   *out = c;
   return TSVD_OK;
 }
@@ -676,6 +723,11 @@ void tsvd_csr_destroy(tsvd_csr* c) {
   hipSetDevice(c->device);
   hipDeviceSynchronize();
   hipFree(c->colptr);
+  for (int dir = 0; dir < 2; dir++) {
+    hipFree(c->tptr[dir]);
+    hipFree(c->tkey[dir]);
+    hipFree(c->tval[dir]);
+  }
   hipFree(c->rowidx);
   hipFree(c->cval);
   delete c;
@@ -700,10 +752,7 @@ tsvd_status tsvd_spmv(tsvd_ctx* ctx, const tsvd_csr* c, int32_t trans, const voi
   if (trans != 0 && trans != 1) return fail(ctx, TSVD_ERR_INVALID_ARG, "trans must be 0 or 1");
   if (x_dtype != TSVD_F32 && x_dtype != TSVD_F64) return fail(ctx, TSVD_ERR_INVALID_ARG, "bad x dtype");
   hipSetDevice(ctx->device);
-  int rc = trans == 0 ? spmv_launch(c->rowptr, c->col, c->val, x, x_dtype == TSVD_F64, c->m, c->nnz, y, nullptr,
-                                    (hipStream_t)stream)
-                      : spmv_launch(c->colptr, c->rowidx, c->cval, x, x_dtype == TSVD_F64, c->n, c->nnz, y, nullptr,
-                                    (hipStream_t)stream);
+  int rc = csr_product(c, trans, x, x_dtype == TSVD_F64, y, nullptr, (hipStream_t)stream);
   return from_internal(ctx, rc, "spmv");
 }
 
@@ -740,19 +789,12 @@ tsvd_status tsvd_sparse(tsvd_ctx* ctx, const tsvd_csr* c, const tsvd_opts* o, do
   double* w = (double*)bump.take((size_t)d * 8);    // product, projected in place
   float* xf = (float*)bump.take((size_t)d * 4);     // FP32 copy gathered by the first product
   float* tf = (float*)bump.take((size_t)e * 4);     // intermediate A x (or A^T x) in FP32
-  double* partial = (double*)bump.take((size_t)nb * (k + 2) * 8);
+  double* partial = (double*)bump.take((size_t)std::max<int64_t>(nb * (k + 2), 2 * (int64_t)k) * 8);
   double* coef = (double*)bump.take((size_t)(k + 8) * 8);
   double* scal = (double*)bump.take((size_t)(k + 8) * 8);
 
-  // first product gathers x through (idx1 < d), second through (idx2 < e)
-  const int64_t* p1 = right ? c->rowptr : c->colptr;
-  const int32_t* i1 = right ? c->col : c->rowidx;
-  const float* v1 = right ? c->val : c->cval;
-  const int64_t r1 = right ? m : n;
-  const int64_t* p2 = right ? c->colptr : c->rowptr;
-  const int32_t* i2 = right ? c->rowidx : c->col;
-  const float* v2 = right ? c->cval : c->val;
-  const int64_t r2 = right ? n : m;
+  // right branch: t = A x, w = A^T t; left branch: t = A^T x, w = A t
+  const int dir1 = right ? 0 : 1, dir2 = right ? 1 : 0;
 
   hipEventRecord(ctx->ev[0], s);
   if (hipMemset2DAsync(U, ldu * 8, 0, m * 8, k, s) != hipSuccess ||
@@ -779,8 +821,8 @@ tsvd_status tsvd_sparse(tsvd_ctx* ctx, const tsvd_csr* c, const tsvd_opts* o, do
     double nrm = 0.0;
     bool conv = false;
     while (true) {
-      if ((rc = spmv_launch(p1, i1, v1, xf, 0, r1, c->nnz, nullptr, tf, s))) break;
-      if ((rc = spmv_launch(p2, i2, v2, tf, 0, r2, c->nnz, w, nullptr, s))) break;
+      if ((rc = csr_product(c, dir1, xf, 0, nullptr, tf, s))) break;
+      if ((rc = csr_product(c, dir2, tf, 0, w, nullptr, s))) break;
       it++;
       if ((rc = proj_partials_launch(X, ldx, l, w, x, d, partial, coef, s))) break;
       if ((rc = proj_apply_launch(X, ldx, l, coef, w, d, partial, scal, s))) break;
@@ -826,11 +868,11 @@ tsvd_status tsvd_sparse(tsvd_ctx* ctx, const tsvd_csr* c, const tsvd_opts* o, do
   // sigma_j = ||W[:, j]||, then scale and sign convention
   for (int j = 0; j < kdone && !rc; j++) {
     double* wj = W + (int64_t)j * ldw;
-    rc = spmv_launch(p1, i1, v1, X + (int64_t)j * ldx, 1, r1, c->nnz, wj, nullptr, s);
+    rc = csr_product(c, dir1, X + (int64_t)j * ldx, 1, wj, nullptr, s);
     if (!rc) rc = sumsq_launch(wj, e, partial, S + j, s);
   }
   if (!rc && kdone > 0) rc = sqrt_inplace_launch(S, kdone, s);
-  if (!rc && kdone > 0) rc = finish_scale_sign_launch(W, ldw, e, S, V, ldv, n, U, ldu, m, kdone, 1, s);
+  if (!rc && kdone > 0) rc = finish_scale_sign_launch(W, ldw, e, S, V, ldv, n, U, ldu, m, kdone, 1, partial, s);
   if (rc) return from_internal(ctx, rc, "sparse finish");
   hipEventRecord(ctx->ev[3], s);
   if (hipStreamSynchronize(s) != hipSuccess) return fail(ctx, TSVD_ERR_HIP, "sync");

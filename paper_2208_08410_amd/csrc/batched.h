@@ -22,30 +22,19 @@ struct ProbPlan {
   int nb = 0;                 // finish row tiles
   // per-problem workspace: offsets from the problem's base, total bytes
   size_t off_B = 0, off_partial = 0, off_ssq = 0, ws_bytes = 0;
-};
-
-struct TeamPlan {
-  int size = 0, first = 0;
-  double load = 0.0;
-  std::vector<int> probs;  // problem indices, in run order
-  int dpad_max = 0, k_max = 0;
-  size_t off_ex = 0, off_kscr = 0;  // in the batch workspace
-};
-
-struct RoundPlan {
-  std::vector<TeamPlan> teams;
-  int grid = 0;
-  int team0 = 0, tob0 = 0;  // offsets into the device team / block tables
+  // power exchange buffers and scratch, in the batch workspace
+  size_t off_ex = 0, ex_words = 0, off_kscr = 0;
 };
 
 struct BatchPlan {
   int count = 0;
   std::vector<ProbPlan> P;
-  std::vector<RoundPlan> rounds;
-  int nteams = 0, ntob = 0;
+  std::vector<int> queue;   // power queue: problem indices, longest first
+  int grid = 0;             // power workgroups
   // batch workspace layout
-  size_t off_gjobs = 0, off_pargs = 0, off_order = 0, off_teams = 0, off_tob = 0, off_fjobs = 0, desc_bytes = 0;
-  size_t off_status = 0, off_iters = 0, off_lambda = 0, off_fixed = 0, off_ex = 0, ex_words = 0;
+  size_t off_gjobs = 0, off_pargs = 0, off_order = 0, off_gsize = 0, off_fjobs = 0, desc_bytes = 0;
+  size_t off_status = 0, off_iters = 0, off_lambda = 0, off_fixed = 0;
+  size_t off_zero = 0, zero_words = 0, off_sched = 0;  // cleared before the power launch
   size_t batch_ws_bytes = 0;
   size_t total_k = 0;
   // filled by batch_enqueue (host copies live until the stream completes)

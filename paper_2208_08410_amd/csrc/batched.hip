@@ -6,17 +6,17 @@
 //   Gram:   one launch per (Gram mode, side) whose workgroups are the
 //           (problem, split-K chunk, 128x128 triangle tile) units of every
 //           problem, then one deterministic reduction launch.
-//   Power:  cooperative launches ("rounds"); in each, the CUs are split into
-//           teams and every team solves its list of problems one after the
-//           other with its own exchange buffers (a team is to one problem what
+//   Power:  one cooperative launch; workgroups form a team for each problem
+//           as they come free (problems queued longest first) and the team
+//           runs the single-problem body on it (a team is to one problem what
 //           the whole grid is to a single call).
 //   Finish: one grouped FP64 product launch per side, then sigma and scale/sign.
 //
 // A problem's team size depends only on its own Gram dimension and the
-// context's team_kib (teams host only problems of their own size), and its
-// Gram chunking only on its own contraction length, so its result does not
-// depend on which other problems share the batch: a problem solved alone and
-// in any mix gives the same bits.
+// context's team_kib, a member's rows only on its rank in the team, and the
+// Gram chunking only on the problem's contraction length, so its result does
+// not depend on which other problems share the batch: a problem solved alone
+// and in any mix gives the same bits.
 #include <math.h>
 #include <string.h>
 
@@ -47,58 +47,6 @@ int wanted_team(int64_t d, int num_cu, int team_kib) {
 // d x d Gram split g ways, with a floor for the exchange latency
 double team_cost(int64_t d, int k, int g) { return (double)k * std::max((double)d * (double)d / g, 65536.0); }
 
-// Rounds of teams.  Problems are taken longest first; each joins the
-// least-loaded team of its own size in the current round if that finishes no
-// later than the round's longest team, else opens a new team while CUs remain,
-// else waits for the next round.
-void plan_rounds(std::vector<ProbPlan>& P, int num_cu, std::vector<RoundPlan>& rounds) {
-  std::vector<int> todo(P.size());
-  std::iota(todo.begin(), todo.end(), 0);
-  std::stable_sort(todo.begin(), todo.end(), [&](int a, int b) {
-    return team_cost(P[a].d, P[a].k, P[a].G) > team_cost(P[b].d, P[b].k, P[b].G);
-  });
-  while (!todo.empty()) {
-    RoundPlan r;
-    int free_cu = num_cu;
-    double longest = 0.0;
-    std::vector<int> later;
-    for (int i : todo) {
-      const double c = team_cost(P[i].d, P[i].k, P[i].G);
-      int best = -1;
-      double best_end = 1e300;
-      for (size_t t = 0; t < r.teams.size(); t++) {
-        if (r.teams[t].size != P[i].G) continue;
-        const double end = r.teams[t].load + c;
-        if (end < best_end) { best_end = end; best = (int)t; }
-      }
-      if (best >= 0 && best_end <= std::max(longest, c)) {
-        r.teams[best].probs.push_back(i);
-        r.teams[best].load = best_end;
-        longest = std::max(longest, best_end);
-      } else if (free_cu >= P[i].G) {
-        TeamPlan t;
-        t.size = P[i].G;
-        t.first = num_cu - free_cu;
-        free_cu -= P[i].G;
-        t.probs.push_back(i);
-        t.load = c;
-        longest = std::max(longest, c);
-        r.teams.push_back(t);
-      } else if (best >= 0) {
-        r.teams[best].probs.push_back(i);
-        r.teams[best].load = best_end;
-        longest = std::max(longest, best_end);
-      } else {
-        later.push_back(i);
-      }
-    }
-    r.grid = 0;
-    for (auto& t : r.teams) r.grid = std::max(r.grid, t.first + t.size);
-    rounds.push_back(std::move(r));
-    todo.swap(later);
-  }
-}
-
 }  // namespace
 
 tsvd_status batch_plan(tsvd_ctx* ctx, int count, const tsvd_problem* probs, BatchPlan& bp) {
@@ -106,7 +54,6 @@ tsvd_status batch_plan(tsvd_ctx* ctx, int count, const tsvd_problem* probs, Batc
   const int64_t kc_target = ctx->tuning.group_kchunk > 0 ? ctx->tuning.group_kchunk : 2048;
   bp.count = count;
   bp.P.assign(count, ProbPlan());
-  bp.rounds.clear();
   for (int i = 0; i < count; i++) {
     const tsvd_problem& q = probs[i];
     const tsvd_opts& o = q.opts;
@@ -158,23 +105,27 @@ tsvd_status batch_plan(tsvd_ctx* ctx, int count, const tsvd_problem* probs, Batc
     auto take = [&](size_t b) { off = align256(off); const size_t o2 = off; off += b; return o2; };
     p.off_B = take((size_t)p.d * p.ldb * 4);
     p.off_partial = take((size_t)p.S * p.T * kTile * kTile * 4);
-    p.off_ssq = take((size_t)p.nb * p.k * 8);
+    p.off_ssq = take((size_t)(p.nb + 2) * p.k * 8);
     p.ws_bytes = align256(off);
   }
-  plan_rounds(bp.P, ctx->num_cu, bp.rounds);
+  // power queue, longest first (stable: ties keep the caller's order)
+  bp.queue.resize(count);
+  std::iota(bp.queue.begin(), bp.queue.end(), 0);
+  std::stable_sort(bp.queue.begin(), bp.queue.end(), [&](int x, int y) {
+    return team_cost(bp.P[x].d, bp.P[x].k, bp.P[x].G) > team_cost(bp.P[y].d, bp.P[y].k, bp.P[y].G);
+  });
+  int64_t seats = 0;
+  for (auto& p : bp.P) seats += p.G;
+  bp.grid = (int)std::min<int64_t>(seats, ctx->num_cu);
 
-  // batch-level workspace: descriptors, statuses and iteration logs, team buffers
+  // batch-level workspace: descriptors, statuses and iteration logs, then the
+  // cleared region (queue counters and every problem's exchange buffers)
   size_t off = 0;
   auto take = [&](size_t b) { off = align256(off); const size_t o2 = off; off += b; return o2; };
-  int nteams = 0, ntob = 0;
-  for (auto& r : bp.rounds) { nteams += (int)r.teams.size(); ntob += r.grid; }
-  bp.nteams = nteams;
-  bp.ntob = ntob;
   bp.off_gjobs = take((size_t)count * sizeof(GramJob));
   bp.off_pargs = take((size_t)count * sizeof(PowerArgs));
   bp.off_order = take((size_t)count * sizeof(int));
-  bp.off_teams = take((size_t)nteams * sizeof(PowerTeam));
-  bp.off_tob = take((size_t)ntob * sizeof(int));
+  bp.off_gsize = take((size_t)count * sizeof(int));
   bp.off_fjobs = take((size_t)count * sizeof(FinishJob));
   bp.total_k = 0;
   for (auto& p : bp.P) bp.total_k += p.k;
@@ -183,19 +134,15 @@ tsvd_status batch_plan(tsvd_ctx* ctx, int count, const tsvd_problem* probs, Batc
   bp.off_status = take((size_t)count * 4 * sizeof(int));
   bp.off_iters = take(bp.total_k * sizeof(int));
   bp.off_lambda = take(bp.total_k * sizeof(double));
-  bp.off_ex = align256(off);
-  for (auto& r : bp.rounds)
-    for (auto& t : r.teams) {
-      for (int i : t.probs) {
-        t.dpad_max = std::max(t.dpad_max, (int)((bp.P[i].d + 3) & ~3));
-        t.k_max = std::max(t.k_max, bp.P[i].k);
-      }
-      const size_t xw = (size_t)t.dpad_max, pw = (size_t)2 * (t.k_max + 2), vs = (size_t)2 * t.dpad_max;
-      t.off_ex = take((2 * xw + 2 * (size_t)t.size * pw + 4 * vs) * 8);
-    }
-  bp.ex_words = (align256(off) - bp.off_ex) / 8;
-  for (auto& r : bp.rounds)
-    for (auto& t : r.teams) t.off_kscr = take((size_t)t.size * 2 * (t.k_max + 2) * 8);
+  bp.off_zero = align256(off);
+  bp.off_sched = take((size_t)(count + 1) * sizeof(int));
+  for (auto& p : bp.P) {
+    const size_t dpad = (size_t)((p.d + 3) & ~3), pw = (size_t)2 * (p.k + 2);
+    p.ex_words = 2 * dpad + 2 * (size_t)p.G * pw + 8 * dpad;  // x (2 parities), partials, v and w
+    p.off_ex = take(p.ex_words * 8);
+  }
+  bp.zero_words = (align256(off) - bp.off_zero) / 8;
+  for (auto& p : bp.P) p.off_kscr = take((size_t)p.G * 2 * (p.k + 2) * 8);
   bp.batch_ws_bytes = align256(off) + 256;
   return TSVD_OK;
 }
@@ -222,9 +169,6 @@ tsvd_status batch_enqueue(tsvd_ctx* ctx, const tsvd_problem* probs, BatchPlan& b
   char* h = bp.desc;
   GramJob* gj = (GramJob*)(h + bp.off_gjobs);
   PowerArgs* pa = (PowerArgs*)(h + bp.off_pargs);
-  int* ord = (int*)(h + bp.off_order);
-  PowerTeam* pt = (PowerTeam*)(h + bp.off_teams);
-  int* tob = (int*)(h + bp.off_tob);
   FinishJob* fj = (FinishJob*)(h + bp.off_fjobs);
   std::vector<size_t> kofs(count);
   {
@@ -259,32 +203,13 @@ tsvd_status batch_enqueue(tsvd_ctx* ctx, const tsvd_problem* probs, BatchPlan& b
         if (g.count) bp.ggroups.push_back(g);
       }
   }
-  // teams, round by round
+  // power queue
   {
-    int oi = 0, ti = 0, bi = 0;
-    for (auto& r : bp.rounds) {
-      r.team0 = ti;
-      r.tob0 = bi;
-      for (int b = 0; b < r.grid; b++) tob[bi + b] = -1;
-      for (auto& tp : r.teams) {
-        PowerTeam& d = pt[ti];
-        d.first = tp.first;
-        d.size = tp.size;
-        d.pbegin = oi;
-        for (int i : tp.probs) ord[oi++] = i;
-        d.pend = oi;
-        d.xwords = tp.dpad_max;  // FP32 iterate: one word per element
-        d.pw = 2 * (tp.k_max + 2);
-        d.vstride = (int64_t)2 * tp.dpad_max;
-        d.xex = (uint64_t*)(bbase + tp.off_ex);
-        d.pex = d.xex + 2 * d.xwords;
-        d.vex = d.pex + (size_t)2 * tp.size * d.pw;
-        d.wex = d.vex + 2 * d.vstride;
-        d.kscr = (double*)(bbase + tp.off_kscr);
-        for (int b = 0; b < tp.size; b++) tob[bi + tp.first + b] = ti - r.team0;
-        ti++;
-      }
-      bi += r.grid;
+    int* ord = (int*)(h + bp.off_order);
+    int* gs = (int*)(h + bp.off_gsize);
+    for (int q = 0; q < count; q++) {
+      ord[q] = bp.queue[q];
+      gs[q] = bp.P[bp.queue[q]].G;
     }
   }
   int* d_status = (int*)(bbase + bp.off_status);
@@ -311,7 +236,15 @@ tsvd_status batch_enqueue(tsvd_ctx* ctx, const tsvd_problem* probs, BatchPlan& b
     a.ldsB = p.pp.ldsB;
     a.vec_ok = 1;  // B is 256-byte aligned with ldb a multiple of 4
     a.spin_limit = (int64_t)1 << 21;
-    // exchange buffers, pw, xwords and vstride come from the team at run time
+    const int64_t dpad = (p.d + 3) & ~(int64_t)3;
+    a.pw = 2 * (p.k + 2);
+    a.xwords = dpad;  // FP32 iterate: one word per element
+    a.vstride = 2 * dpad;
+    a.xex = (uint64_t*)(bbase + p.off_ex);
+    a.pex = a.xex + 2 * a.xwords;
+    a.vex = a.pex + (int64_t)2 * p.G * a.pw;
+    a.wex = a.vex + 2 * a.vstride;
+    a.kscr = (double*)(bbase + p.off_kscr);
   }
   for (int i = 0; i < count; i++)
     if (probs[i].opts.fixed_iters)
@@ -363,20 +296,21 @@ tsvd_status batch_enqueue(tsvd_ctx* ctx, const tsvd_problem* probs, BatchPlan& b
   if (ev && hipEventRecord(ev[1], stream) != hipSuccess) return fail(ctx, TSVD_ERR_HIP, "event");
   size_t lds = 0;
   for (auto& p : bp.P) lds = std::max(lds, p.pp.lds_bytes);
-  for (size_t r = 0; r < bp.rounds.size(); r++) {
-    const RoundPlan& rp = bp.rounds[r];
-    const int rc = power_team_launch((const PowerArgs*)(bbase + bp.off_pargs), (const int*)(bbase + bp.off_order),
-                                     (const PowerTeam*)(bbase + bp.off_teams) + rp.team0,
-                                     (const int*)(bbase + bp.off_tob) + rp.tob0, rp.grid, lds,
-                                     (uint64_t*)(bbase + bp.off_ex), r == 0 ? bp.ex_words : 0, stream);
-    if (rc == -2) return fail(ctx, TSVD_ERR_UNSUPPORTED, "team power kernel does not fit on a CU");
-    if (rc) return from_internal(ctx, rc, "team power iteration");
+  {
+    const int rc = power_dyn_launch((const PowerArgs*)(bbase + bp.off_pargs), (const int*)(bbase + bp.off_order),
+                                    (const int*)(bbase + bp.off_gsize), count, (int*)(bbase + bp.off_sched), bp.grid,
+                                    lds, (uint64_t*)(bbase + bp.off_zero), bp.zero_words, stream);
+    if (rc == -2) return fail(ctx, TSVD_ERR_UNSUPPORTED, "batched power kernel does not fit on a CU");
+    if (rc) return from_internal(ctx, rc, "batched power iteration");
   }
   if (ev && hipEventRecord(ev[2], stream) != hipSuccess) return fail(ctx, TSVD_ERR_HIP, "event");
   {
     const FinishJob* dfj = (const FinishJob*)(bbase + bp.off_fjobs);
-    int rc = finish_grouped_launch(0, dfj, bp.fcount[0], bp.funits[0], bp.fcols[0], stream);
-    if (!rc) rc = finish_grouped_launch(1, dfj + bp.fcount[0], bp.fcount[1], bp.funits[1], bp.fcols[1], stream);
+    int64_t rows[2] = {0, 0};
+    for (int i = 0; i < count; i++) rows[bp.P[i].side] = std::max(rows[bp.P[i].side], std::max(probs[i].m, probs[i].n));
+    int rc = finish_grouped_launch(0, dfj, bp.fcount[0], bp.funits[0], bp.fcols[0], rows[0], stream);
+    if (!rc)
+      rc = finish_grouped_launch(1, dfj + bp.fcount[0], bp.fcount[1], bp.funits[1], bp.fcols[1], rows[1], stream);
     if (rc) return from_internal(ctx, rc, "grouped finish");
   }
   if (ev && hipEventRecord(ev[3], stream) != hipSuccess) return fail(ctx, TSVD_ERR_HIP, "event");

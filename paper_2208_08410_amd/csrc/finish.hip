@@ -5,6 +5,8 @@
 // partial column sums of squares of its rows, which a second kernel adds in
 // workgroup order (deterministic) to give sigma.  A last kernel divides by
 // sigma and applies the sign convention (largest-|.| entry of each v positive).
+#include <algorithm>
+
 #include "common.h"
 #include "internal.h"
 
@@ -177,61 +179,92 @@ __global__ __launch_bounds__(256) void finish_gemm_kernel(const AT* A, int64_t l
   finish_gemm_unit<AT, SIDE>(A, lda, M, K, X, ldx, N, W, ldw, ssq, blockIdx.x, blockIdx.y, vec != 0);
 }
 
-// sigma_j = sqrt(sum over row tiles of ssq[b][j]), added in tile order.
-__global__ void finish_sigma_kernel(const double* ssq, int nb, int N, double* S) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= N) return;
+// sigma_j = sqrt(sum over row tiles of ssq[b][j]): one workgroup per column,
+// thread t adds tiles t, t + 256, ... in order, then a fixed-shape tree.
+__device__ __forceinline__ void sigma_column(const double* ssq, int64_t nb, int N, int j, double* S) {
+  __shared__ double red[256];
+  const int tid = threadIdx.x;
   double t = 0.0;
-  for (int b = 0; b < nb; b++) t += ssq[(int64_t)b * N + j];
-  S[j] = sqrt(t);
+  for (int64_t b = tid; b < nb; b += 256) t += ssq[b * N + j];
+  red[tid] = t;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (tid < off) red[tid] += red[tid + off];
+    __syncthreads();
+  }
+  if (tid == 0) S[j] = sqrt(red[0]);
 }
 
-// Column j: divide W[:, j] by S[j] (zero columns stay zero), then find the
-// largest-|.| entry of V[:, j] (ties: lowest index) and flip V[:, j] and
-// U[:, j] if it is negative.  W aliases U (side RIGHT) or V (side LEFT).
-__device__ __forceinline__ void scale_sign_column(double* W, int64_t ldw, int64_t Mw, const double* S, double* V,
-                                                  int64_t ldv, int64_t n, double* U, int64_t ldu, int64_t m,
-                                                  int do_sign, int j) {
+__global__ __launch_bounds__(256) void finish_sigma_kernel(const double* ssq, int64_t nb, int N, double* S) {
+  sigma_column(ssq, nb, N, blockIdx.x, S);
+}
+
+// Column factors: fac[2j] multiplies W[:, j] (1/sigma_j, negated when the
+// column's sign flips; 0 when sigma_j = 0), fac[2j+1] multiplies the iterate
+// column X[:, j] (+1 or -1).  The sign convention makes the largest-|.| entry
+// of v_j positive (ties: lowest index); v is X (v_from_w = 0, the right
+// branch) or the scaled W (v_from_w = 1, the left branch, where W = V).
+__device__ __forceinline__ void sign_column(const double* W, int64_t ldw, const double* S, const double* X,
+                                            int64_t ldx, int64_t n, int v_from_w, int do_sign, int j, double* fac) {
   const int tid = threadIdx.x;
   const double s = S[j];
   const double inv = s > 0.0 ? 1.0 / s : 0.0;
-  double* w = W + (int64_t)j * ldw;
-  for (int64_t i = tid; i < Mw; i += 256) w[i] = s > 0.0 ? w[i] * inv : 0.0;
-  if (!do_sign) return;
-  __syncthreads();
-  const double* v = V + (int64_t)j * ldv;
-  double best = -1.0;
+  if (!do_sign) {
+    if (tid == 0) { fac[2 * j] = inv; fac[2 * j + 1] = 1.0; }
+    return;
+  }
+  const double* v = v_from_w ? W + (int64_t)j * ldw : X + (int64_t)j * ldx;
+  const double sc = v_from_w ? inv : 1.0;
+  double best = -1.0, bval = 0.0;
   int64_t bi = 0;
   for (int64_t i = tid; i < n; i += 256) {
-    const double a = fabs(v[i]);
-    if (a > best) { best = a; bi = i; }
+    const double val = v[i] * sc;
+    const double a = fabs(val);
+    if (a > best) { best = a; bi = i; bval = val; }
   }
-  __shared__ double sb[256];
+  __shared__ double sb[256], sv[256];
   __shared__ int64_t si[256];
-  sb[tid] = best; si[tid] = bi;
+  sb[tid] = best; si[tid] = bi; sv[tid] = bval;
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
     if (tid < off) {
       const double ob = sb[tid + off];
       const int64_t oi = si[tid + off];
-      if (ob > sb[tid] || (ob == sb[tid] && oi < si[tid])) { sb[tid] = ob; si[tid] = oi; }
+      if (ob > sb[tid] || (ob == sb[tid] && oi < si[tid])) { sb[tid] = ob; si[tid] = oi; sv[tid] = sv[tid + off]; }
     }
     __syncthreads();
   }
-  const bool flip = V[(int64_t)j * ldv + si[0]] < 0.0;
-  __syncthreads();
-  if (flip) {
-    double* vv = V + (int64_t)j * ldv;
-    double* uu = U + (int64_t)j * ldu;
-    for (int64_t i = tid; i < n; i += 256) vv[i] = -vv[i];
-    for (int64_t i = tid; i < m; i += 256) uu[i] = -uu[i];
+  if (tid == 0) {
+    const bool flip = sv[0] < 0.0;
+    fac[2 * j] = flip ? -inv : inv;
+    fac[2 * j + 1] = flip ? -1.0 : 1.0;
   }
 }
 
-__global__ __launch_bounds__(256) void finish_scale_sign_kernel(double* W, int64_t ldw, int64_t Mw, const double* S,
-                                                                double* V, int64_t ldv, int64_t n, double* U,
-                                                                int64_t ldu, int64_t m, int do_sign) {
-  scale_sign_column(W, ldw, Mw, S, V, ldv, n, U, ldu, m, do_sign, blockIdx.x);
+__global__ __launch_bounds__(256) void finish_sign_kernel(const double* W, int64_t ldw, const double* S,
+                                                          const double* X, int64_t ldx, int64_t n, int v_from_w,
+                                                          int do_sign, double* fac) {
+  sign_column(W, ldw, S, X, ldx, n, v_from_w, do_sign, blockIdx.x, fac);
+}
+
+// W[:, j] *= fac[2j] (rows < Mw; exact zeros when sigma_j = 0) and
+// X[:, j] *= fac[2j+1] when that is -1 (rows < Mx); grid (row chunks, columns).
+constexpr int APPLY_ROWS = 2048;
+__device__ __forceinline__ void apply_column(double* W, int64_t ldw, int64_t Mw, double* X, int64_t ldx, int64_t Mx,
+                                             const double* fac, int j, int64_t chunk) {
+  const double f = fac[2 * j], g = fac[2 * j + 1];
+  const int64_t r0 = chunk * APPLY_ROWS;
+  double* w = W + (int64_t)j * ldw;
+  for (int64_t i = r0 + threadIdx.x; i < min(Mw, r0 + APPLY_ROWS); i += 256) w[i] = f != 0.0 ? w[i] * f : 0.0;
+  if (X && g < 0.0) {
+    double* x = X + (int64_t)j * ldx;
+    for (int64_t i = r0 + threadIdx.x; i < min(Mx, r0 + APPLY_ROWS); i += 256) x[i] = -x[i];
+  }
+}
+
+__global__ __launch_bounds__(256) void finish_apply_kernel(double* W, int64_t ldw, int64_t Mw, double* X, int64_t ldx,
+                                                           int64_t Mx, const double* fac) {
+  apply_column(W, ldw, Mw, X, ldx, Mx, fac, blockIdx.y, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -264,42 +297,53 @@ __global__ __launch_bounds__(256) void finish_grouped_gemm_kernel(const FinishJo
   finish_gemm_unit<float, SIDE>((const float*)j.A, j.lda, M, K, X, ldx, j.k, W, ldw, j.ssq, u % j.nb, u / j.nb, vec);
 }
 
-__global__ void finish_grouped_sigma_kernel(const FinishJob* jobs) {
-  const FinishJob& j = jobs[blockIdx.x];
-  for (int c = threadIdx.x; c < j.k; c += blockDim.x) {
-    double t = 0.0;
-    for (int b = 0; b < j.nb; b++) t += j.ssq[(int64_t)b * j.k + c];
-    j.S[c] = sqrt(t);
-  }
+// workgroup -> (job, column) through cbegin
+__global__ __launch_bounds__(256) void finish_grouped_sigma_kernel(const FinishJob* jobs, int njobs) {
+  const FinishJob& j = jobs[find_fjob(jobs, njobs, blockIdx.x, 1)];
+  sigma_column(j.ssq, j.nb, j.k, (int)(blockIdx.x - j.cbegin), j.S);
 }
 
-__global__ __launch_bounds__(256) void finish_grouped_scale_kernel(const FinishJob* jobs, int njobs) {
-  const int jb = find_fjob(jobs, njobs, blockIdx.x, 1);
-  const FinishJob& j = jobs[jb];
+__global__ __launch_bounds__(256) void finish_grouped_sign_kernel(const FinishJob* jobs, int njobs) {
+  const FinishJob& j = jobs[find_fjob(jobs, njobs, blockIdx.x, 1)];
   const int c = (int)(blockIdx.x - j.cbegin);
   if (c >= *j.kdone) return;
-  double* W = j.side == 0 ? j.U : j.V;
-  const int64_t ldw = j.side == 0 ? j.ldu : j.ldv;
-  const int64_t Mw = j.side == 0 ? j.m : j.n;
-  scale_sign_column(W, ldw, Mw, j.S, j.V, j.ldv, j.n, j.U, j.ldu, j.m, 1, c);
+  double* fac = j.ssq + (int64_t)j.nb * j.k;
+  if (j.side == 0) sign_column(j.U, j.ldu, j.S, j.V, j.ldv, j.n, 0, 1, c, fac);
+  else sign_column(j.V, j.ldv, j.S, j.U, j.ldu, j.n, 1, 1, c, fac);
 }
 
-int finish_grouped_launch(int side, const FinishJob* d_jobs, int njobs, int64_t units, int64_t cols, hipStream_t s) {
+// grid (row chunks of the longest column, total columns)
+__global__ __launch_bounds__(256) void finish_grouped_apply_kernel(const FinishJob* jobs, int njobs) {
+  const FinishJob& j = jobs[find_fjob(jobs, njobs, blockIdx.y, 1)];
+  const int c = (int)(blockIdx.y - j.cbegin);
+  if (c >= *j.kdone) return;
+  const double* fac = j.ssq + (int64_t)j.nb * j.k;
+  if (j.side == 0) apply_column(j.U, j.ldu, j.m, j.V, j.ldv, j.n, fac, c, blockIdx.x);
+  else apply_column(j.V, j.ldv, j.n, j.U, j.ldu, j.m, fac, c, blockIdx.x);
+}
+
+int finish_grouped_launch(int side, const FinishJob* d_jobs, int njobs, int64_t units, int64_t cols, int64_t max_rows,
+                          hipStream_t s) {
   if (njobs <= 0) return 0;
   if (side == 0) hipLaunchKernelGGL(finish_grouped_gemm_kernel<0>, dim3((unsigned)units), dim3(256), 0, s, d_jobs, njobs);
   else hipLaunchKernelGGL(finish_grouped_gemm_kernel<1>, dim3((unsigned)units), dim3(256), 0, s, d_jobs, njobs);
   TSVD_HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(finish_grouped_sigma_kernel, dim3(njobs), dim3(64), 0, s, d_jobs);
+  hipLaunchKernelGGL(finish_grouped_sigma_kernel, dim3((unsigned)cols), dim3(256), 0, s, d_jobs, njobs);
   TSVD_HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(finish_grouped_scale_kernel, dim3((unsigned)cols), dim3(256), 0, s, d_jobs, njobs);
+  hipLaunchKernelGGL(finish_grouped_sign_kernel, dim3((unsigned)cols), dim3(256), 0, s, d_jobs, njobs);
+  TSVD_HIP_TRY(hipGetLastError());
+  const unsigned chunks = (unsigned)((max_rows + APPLY_ROWS - 1) / APPLY_ROWS);
+  hipLaunchKernelGGL(finish_grouped_apply_kernel, dim3(chunks, (unsigned)cols), dim3(256), 0, s, d_jobs, njobs);
   TSVD_HIP_TRY(hipGetLastError());
   return 0;
 }
 
-int finish_workspace_doubles(int64_t m, int64_t n, int side, int k) {
+int64_t finish_tiles(int64_t m, int64_t n, int side) {
   const int64_t M = side == 0 ? m : n;
-  const int64_t nb = (M + FBM - 1) / FBM;
-  return (int)(nb * k);
+  return (M + FBM - 1) / FBM;
+}
+int64_t finish_workspace_doubles(int64_t m, int64_t n, int side, int k) {
+  return (finish_tiles(m, n, side) + 2) * k;  // column sums per row tile, then 2 factors per column
 }
 
 int finish_gemm_launch(int is_f64, int side, const void* A, int64_t m, int64_t n, int64_t lda, const double* X,
@@ -329,7 +373,8 @@ int finish_gemm_launch(int is_f64, int side, const void* A, int64_t m, int64_t n
 }
 
 int finish_sigma_launch(const double* ssq, int64_t nb, int k, double* S, hipStream_t stream) {
-  hipLaunchKernelGGL(finish_sigma_kernel, dim3((k + 127) / 128), dim3(128), 0, stream, ssq, (int)nb, k, S);
+  if (k <= 0) return 0;
+  hipLaunchKernelGGL(finish_sigma_kernel, dim3(k), dim3(256), 0, stream, ssq, nb, k, S);
   TSVD_HIP_TRY(hipGetLastError());
   return 0;
 }
@@ -343,10 +388,18 @@ int finish_launch(int is_f64, int side, const void* A, int64_t m, int64_t n, int
 }
 
 int finish_scale_sign_launch(double* W, int64_t ldw, int64_t Mw, const double* S, double* V, int64_t ldv, int64_t n,
-                             double* U, int64_t ldu, int64_t m, int k, int do_sign, hipStream_t stream) {
+                             double* U, int64_t ldu, int64_t m, int k, int do_sign, double* fac, hipStream_t stream) {
   if (k <= 0) return 0;
-  hipLaunchKernelGGL(finish_scale_sign_kernel, dim3(k), dim3(256), 0, stream, W, ldw, Mw, S, V, ldv, n, U, ldu, m,
-                     do_sign);
+  // W aliases U (right branch: the iterate X is V) or V (left branch: X is U)
+  const bool w_is_v = (W == V);
+  double* X = do_sign ? (w_is_v ? U : V) : nullptr;
+  const int64_t ldx = w_is_v ? ldu : ldv, Mx = w_is_v ? m : n;
+  hipLaunchKernelGGL(finish_sign_kernel, dim3(k), dim3(256), 0, stream, W, ldw, S, X, ldx, n, w_is_v ? 1 : 0, do_sign,
+                     fac);
+  TSVD_HIP_TRY(hipGetLastError());
+  const int64_t rows = std::max(Mw, do_sign ? Mx : (int64_t)0);
+  hipLaunchKernelGGL(finish_apply_kernel, dim3((unsigned)((rows + APPLY_ROWS - 1) / APPLY_ROWS), (unsigned)k), dim3(256),
+                     0, stream, W, ldw, Mw, X, ldx, Mx, fac);
   TSVD_HIP_TRY(hipGetLastError());
   return 0;
 }

@@ -64,19 +64,6 @@ struct PowerArgs {
   int64_t xwords;           // words per parity of xex
   int64_t vstride;          // words per parity of vex / wex
 };
-// A team of the batched power launch: workgroups [first, first + size) solve
-// problems order[pbegin..pend) with their own exchange buffers.
-struct PowerTeam {
-  int first, size, pbegin, pend;
-  uint64_t* xex;
-  uint64_t* pex;
-  uint64_t* vex;
-  uint64_t* wex;
-  double* kscr;
-  int pw;
-  int pad;
-  int64_t xwords, vstride;
-};
 struct PowerPlan {
   int G, rpb, cache_rows, ldsB, pw;
   size_t lds_bytes;
@@ -85,11 +72,12 @@ struct PowerPlan {
 enum { ERR_NONE = 0, ERR_SPIN = 1, ERR_NONFINITE = 2, ERR_BADSTART = 3 };
 int power_plan(int dtype_bytes, int d, int k, int num_cu, size_t max_lds, int max_blocks_hint, PowerPlan* p);
 int power_launch(int is_f64, const PowerPlan& p, PowerArgs a, hipStream_t stream);
-// batched launch (FP32 Grams): grid = total team workgroups (co-resident,
-// cooperative); zero_words of exchange memory at zero_base are cleared first
-int power_team_launch(const PowerArgs* d_probs, const int* d_order, const PowerTeam* d_teams,
-                      const int* d_team_of_block, int grid, size_t lds_bytes, uint64_t* zero_base, size_t zero_words,
-                      hipStream_t stream);
+// batched launch (FP32 Grams), teams formed on the fly: problems order[0..n)
+// (queue order) with team sizes gsize[h]; sched holds 1 + n ints, zero on
+// entry; grid workgroups, one per CU (cooperative); zero_words of exchange
+// memory at zero_base are cleared first
+int power_dyn_launch(const PowerArgs* d_probs, const int* d_order, const int* d_gsize, int nprob, int* d_sched,
+                     int grid, size_t lds_bytes, uint64_t* zero_base, size_t zero_words, hipStream_t stream);
 
 // ---- finishing pass (finish.hip)
 // one problem of a grouped finishing pass (FP32 A); k = triplets found
@@ -102,21 +90,27 @@ struct FinishJob {
   double* V;
   int64_t ldv;
   double* S;
-  double* ssq;           // nb * k
+  double* ssq;           // (nb + 2) * k: column sums per row tile, then 2 factors per column
   const int* kdone;      // device: triplets the power phase produced (columns to scale)
   int nb, pad;           // row tiles of the product
   int64_t ubegin;        // first workgroup in the product launch (nb * column blocks units)
   int64_t cbegin;        // first workgroup in the scale launch (k units)
 };
-int finish_grouped_launch(int side, const FinishJob* d_jobs, int njobs, int64_t units, int64_t cols, hipStream_t s);
-int finish_workspace_doubles(int64_t m, int64_t n, int side, int k);
+// max_rows: the longest U or V column among the jobs (rows of the apply grid)
+int finish_grouped_launch(int side, const FinishJob* d_jobs, int njobs, int64_t units, int64_t cols, int64_t max_rows,
+                          hipStream_t s);
+// row tiles of the finishing product; workspace = (tiles + 2) * k doubles:
+// column sums of squares per tile, then the scale/sign factors
+int64_t finish_tiles(int64_t m, int64_t n, int side);
+int64_t finish_workspace_doubles(int64_t m, int64_t n, int side, int k);
 int finish_gemm_launch(int is_f64, int side, const void* A, int64_t m, int64_t n, int64_t lda, const double* X,
                        int64_t ldx, int k, double* W, int64_t ldw, double* ssq, hipStream_t stream);
 int finish_sigma_launch(const double* ssq, int64_t nb, int k, double* S, hipStream_t stream);
 int finish_launch(int is_f64, int side, const void* A, int64_t m, int64_t n, int64_t lda, const double* X,
                   int64_t ldx, int k, double* W, int64_t ldw, double* S, double* ssq, hipStream_t stream);
+// fac: 2k doubles of scratch
 int finish_scale_sign_launch(double* W, int64_t ldw, int64_t Mw, const double* S, double* V, int64_t ldv, int64_t n,
-                             double* U, int64_t ldu, int64_t m, int k, int do_sign, hipStream_t stream);
+                             double* U, int64_t ldu, int64_t m, int k, int do_sign, double* fac, hipStream_t stream);
 
 // ---- sparse path (sparse.hip)
 int csr_validate(const int64_t* rowptr, const int32_t* col, int64_t m, int64_t n, int64_t nnz, int* d_bad,
@@ -126,6 +120,23 @@ int csc_build(const int64_t* rowptr, const int32_t* col, const float* val, int64
               int64_t* colptr, int32_t* rowidx, float* cval, void* scratch, hipStream_t s);
 int spmv_launch(const int64_t* ptr, const int32_t* idx, const float* val, const void* x, int x_is_f64, int64_t rows,
                 int64_t nnz, double* y, float* yf, hipStream_t s);
+// exclusive scan of n counts into out[0..n] (out[n] = total); bsum: (n + 1023) / 1024 + 1 entries
+int scan_counts(const unsigned long long* cnt, int64_t n, unsigned long long* bsum, int64_t* out, int64_t total,
+                hipStream_t s);
+
+// ---- sliced tiles for the sparse products (tiles.hip)
+struct TilePlan {
+  int rbits, cbits;          // tile = 2^rbits rows x 2^cbits columns
+  int64_t nchunks, nslices;  // row chunks, column slices
+};
+// rbits_hint / cbits_hint: 0 = library choice; returns -1 for an impossible request
+int tiles_plan(int64_t rows, int64_t cols, int num_cu, int rbits_hint, int cbits_hint, TilePlan* t);
+size_t tiles_scratch_bytes(const TilePlan& t);
+// tptr: nchunks * nslices + 1 int64; key, tval: nnz each
+int tiles_build(const int64_t* ptr, const int32_t* idx, const float* val, int64_t rows, int64_t nnz,
+                const TilePlan& t, int64_t* tptr, uint32_t* key, float* tval, void* scratch, hipStream_t s);
+int spmv_tiles_launch(const TilePlan& t, const int64_t* tptr, const uint32_t* key, const float* val, int64_t rows,
+                      const void* x, int x_is_f64, double* y, float* yf, hipStream_t s);
 int64_t proj_blocks(int64_t d);
 int proj_partials_launch(const double* V, int64_t ldv, int l, const double* w, const double* x, int64_t d,
                          double* partial, double* out, hipStream_t s);

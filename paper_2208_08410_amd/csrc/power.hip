@@ -27,6 +27,8 @@
 // HBM) and rounded once to B's storage type.
 #include <math.h>
 
+#include <type_traits>
+
 #include "common.h"
 #include "internal.h"
 
@@ -52,10 +54,17 @@ __device__ __forceinline__ void load_vec<double>(const double* p, double (&v)[2]
 // y[li] = B row li . x for rows li in [begin, end) of one storage (LDS or HBM).
 // Rows are dealt to the 4 waves round-robin (wave w: begin + w + 4j); a wave
 // takes 4 of its rows per pass so each x chunk read from LDS feeds 4 rows.
-template <typename BT>
+// The column loop is unrolled UNR times (deeper for rows read from HBM, so
+// that more loads are in flight).  Each lane keeps one accumulator per (row,
+// vector component) in B's type:
+// 16 independent FMA chains for FP32 (one wave per SIMD has no other wave to
+// hide FMA and LDS latency behind), about d / 256 products per chain; the
+// chains and lanes are then added in FP64.
+template <typename BT, int UNR = 2>
 __device__ void gemv_range(const BT* rows, int64_t stride, int begin, int end, const BT* xs, int d, bool vec_ok,
                            double* yout) {
   constexpr int VN = VecOf<BT>::N;
+  using VT = typename std::conditional<sizeof(BT) == 4, float4, double2>::type;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int dv = vec_ok ? (d / VN) * VN : 0;
   for (int j0 = 0; begin + wave + 4 * j0 < end; j0 += 4) {
@@ -66,33 +75,49 @@ __device__ void gemv_range(const BT* rows, int64_t stride, int begin, int end, c
       li[q] = begin + wave + 4 * (j0 + q);
       if (li[q] < end) nr = q + 1;
     }
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    BT acc[4][VN];
+#pragma unroll
+    for (int q = 0; q < 4; q++)
+#pragma unroll
+      for (int e = 0; e < VN; e++) acc[q][e] = (BT)0;
     const BT* rp[4];
 #pragma unroll
     for (int q = 0; q < 4; q++) rp[q] = rows + (int64_t)(q < nr ? li[q] : li[0]) * stride;
+#pragma unroll UNR
     for (int c = lane * VN; c < dv; c += 64 * VN) {
-      double xv[VN];
-      load_vec<BT>(xs + c, xv);
+      const VT xv = *(const VT*)(xs + c);
+      VT bv[4];
+#pragma unroll
+      for (int q = 0; q < 4; q++)
+        if (q < nr) bv[q] = *(const VT*)(rp[q] + c);
 #pragma unroll
       for (int q = 0; q < 4; q++) {
         if (q < nr) {
-          double bv[VN];
-          load_vec<BT>(rp[q] + c, bv);
-#pragma unroll
-          for (int e = 0; e < VN; e++) acc[q] = fma(bv[e], xv[e], acc[q]);
+          if constexpr (VN == 4) {
+            acc[q][0] = fma(bv[q].x, xv.x, acc[q][0]);
+            acc[q][1] = fma(bv[q].y, xv.y, acc[q][1]);
+            acc[q][2] = fma(bv[q].z, xv.z, acc[q][2]);
+            acc[q][3] = fma(bv[q].w, xv.w, acc[q][3]);
+          } else {
+            acc[q][0] = fma(bv[q].x, xv.x, acc[q][0]);
+            acc[q][1] = fma(bv[q].y, xv.y, acc[q][1]);
+          }
         }
       }
     }
     for (int c = dv + lane; c < d; c += 64) {
-      const double xv = (double)xs[c];
+      const BT xv = xs[c];
 #pragma unroll
       for (int q = 0; q < 4; q++)
-        if (q < nr) acc[q] = fma((double)rp[q][c], xv, acc[q]);
+        if (q < nr) acc[q][0] = fma(rp[q][c], xv, acc[q][0]);
     }
 #pragma unroll
     for (int q = 0; q < 4; q++) {
-      double s = wave_sum(acc[q]);
-      if (lane == 0 && q < nr) yout[li[q]] = s;
+      double t = 0.0;
+#pragma unroll
+      for (int e = 0; e < VN; e++) t += (double)acc[q][e];
+      const double sum = wave_sum(t);
+      if (lane == 0 && q < nr) yout[li[q]] = sum;
     }
   }
 }
@@ -109,13 +134,15 @@ template <typename BT, int NV, int RR>
 __device__ __forceinline__ void gemv_regrows(const RegRows<BT, NV, RR>& R, int cr, int nreg, const BT* xs,
                                              double* yout) {
   if constexpr (RR > 0 && NV > 0) {
-    // per-lane partial sums in BT (64 products per row per lane at d = 4096),
-    // summed across lanes in FP64
+    // per-lane partial sums in BT (16 products per chain at d = 4096),
+    // summed across chains and lanes in FP64
     constexpr int VN = VecOf<BT>::N;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    BT acc[RR];
+    BT acc[RR][VN];  // one FMA chain per (row, component)
 #pragma unroll
-    for (int q = 0; q < RR; q++) acc[q] = (BT)0;
+    for (int q = 0; q < RR; q++)
+#pragma unroll
+      for (int e = 0; e < VN; e++) acc[q][e] = (BT)0;
 #pragma unroll
     for (int s = 0; s < NV; s++) {
       BT xv[VN];
@@ -129,12 +156,15 @@ __device__ __forceinline__ void gemv_regrows(const RegRows<BT, NV, RR>& R, int c
 #pragma unroll
       for (int q = 0; q < RR; q++)
 #pragma unroll
-        for (int e = 0; e < VN; e++) acc[q] = fma(R.v[q][s][e], xv[e], acc[q]);
+        for (int e = 0; e < VN; e++) acc[q][e] = fma(R.v[q][s][e], xv[e], acc[q][e]);
     }
 #pragma unroll
     for (int q = 0; q < RR; q++) {
       const int li = wave + 4 * q;
-      double sum = wave_sum((double)acc[q]);
+      double t = 0.0;
+#pragma unroll
+      for (int e = 0; e < VN; e++) t += (double)acc[q][e];
+      double sum = wave_sum(t);
       if (lane == 0 && li < nreg) yout[cr + li] = sum;
     }
   }
@@ -261,11 +291,12 @@ __device__ bool gather_f64_as(const uint64_t* buf, uint32_t ex, int d, BT* dst, 
 // block to spread the requests over memory channels) and every block's two
 // partials are published; y lands in xs (raw), partials are summed with a
 // fixed-shape tree.  Returns false (block-uniform) on a timed-out wait.
-template <typename BT>
+// W words per thread per round: 16 puts up to 4096 words in flight at once
+// (one round for a 4096-entry FP32 iterate), 8 keeps registers for smaller d.
+template <typename BT, int W>
 __device__ bool gather_iteration(const uint64_t* xb, const uint64_t* pb, uint32_t ex, int d, int b, int G, BT* xs,
                                  double* red, int* flag, int64_t spin_limit, double& q, double& dd) {
   constexpr int WPE = sizeof(BT) / 4;
-  constexpr int W = 8;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int count = d * WPE;
   const int rot = (int)(((int64_t)b * 1031) % count);
@@ -457,7 +488,7 @@ __device__ int solve_problem(const PowerArgs& a, int b, int G, unsigned char* sm
       // ---- y = B x on the block's rows
       gemv_regrows<BT, NV, RR>(R, cr, nreg, xs, yv);
       gemv_range<BT>(Bs, a.ldsB, 0, cr, xs, d, true, yv);
-      gemv_range<BT>(Bg, a.ldb, g0, nrows, xs, d, a.vec_ok != 0, yv);
+      gemv_range<BT, (RR > 0 ? 2 : 8)>(Bg, a.ldb, g0, nrows, xs, d, a.vec_ok != 0, yv);
       __syncthreads();
       it++;
       // ---- publish y (own rows) and the block partials ||y_R||^2, x_R . y_R
@@ -477,7 +508,11 @@ __device__ int solve_problem(const PowerArgs& a, int b, int G, unsigned char* sm
       }
       // ---- one wait for every block's y and partials
       double q, dd;
-      if (!gather_iteration<BT>(xb, pb, epoch, d, b, G, xs, redw, flag, a.spin_limit, q, dd)) { err = ERR_SPIN; break; }
+      // (the widest register-row configuration has no registers to spare for W = 16)
+      const bool got = (NV <= 16 && d * (int)(sizeof(BT) / 4) > 256 * 8)
+                           ? gather_iteration<BT, 16>(xb, pb, epoch, d, b, G, xs, redw, flag, a.spin_limit, q, dd)
+                           : gather_iteration<BT, 8>(xb, pb, epoch, d, b, G, xs, redw, flag, a.spin_limit, q, dd);
+      if (!got) { err = ERR_SPIN; break; }
       nrm = sqrt(q);
       if (!isfinite(nrm)) { err = ERR_NONFINITE; break; }
       if (nrm == 0.0) { rankdef = true; kdone = l; break; }
@@ -569,7 +604,7 @@ __device__ int solve_problem(const PowerArgs& a, int b, int G, unsigned char* sm
     for (int i = tid; i < nrows; i += 256) ll_store_f64(vb + 2 * (int64_t)(r0 + i), epoch, vv[i]);
     if (!gather_f64_as<BT>(vb, epoch, d, xs, flag, a.spin_limit)) { err = ERR_SPIN; break; }
     gemv_range<BT>(Bs, a.ldsB, 0, cr, xs, d, true, wv);
-    gemv_range<BT>(Bg, a.ldb, cr, nrows, xs, d, a.vec_ok != 0, wv);
+    gemv_range<BT, (RR > 0 ? 2 : 8)>(Bg, a.ldb, cr, nrows, xs, d, a.vec_ok != 0, wv);
     __syncthreads();
     if (tid == 0) {
       double al = 0.0;
@@ -616,25 +651,53 @@ __global__ __launch_bounds__(256, 1) void power_kernel(PowerArgs a) {
   solve_problem<BT, NV, RR>(a, blockIdx.x, gridDim.x, smem, epoch, nx, np);
 }
 
-// Batch of problems: the grid is split into teams (contiguous workgroup
-// ranges); each team solves its list of problems one after the other, with
-// its own exchange buffers.  Teams never wait on each other.
-__global__ __launch_bounds__(256, 1) void power_team_kernel(const PowerArgs* probs, const int* order,
-                                                            const PowerTeam* teams, const int* team_of_block) {
+// Batch of problems with teams formed on the fly.  The problems sit in a
+// queue (longest first); problem h needs gsize[h] workgroups.  A free
+// workgroup takes the next seat of the queue head (its rank in that team is
+// its seat number) and moves the head on when the problem is full.  Once all
+// seats are taken the team runs the single-problem body with the problem's own
+// exchange buffers and counters starting from zero, then its members go back
+// to the queue.  A problem's arithmetic depends only on its team size and the
+// ranks, never on which workgroups served it, so results are the same in any
+// mix.  sched: [0] queue head, [1 + h] seats taken in problem h (zeroed by the
+// host).  The assembly wait is bounded by join_spin polls.
+__global__ __launch_bounds__(256, 1) void power_dyn_kernel(const PowerArgs* probs, const int* order, const int* gsize,
+                                                           int nprob, int* sched, int64_t join_spin) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int t = team_of_block[blockIdx.x];
-  if (t < 0) return;
-  const PowerTeam td = teams[t];
-  const int b = blockIdx.x - td.first;
-  uint32_t epoch = 0, nx = 0, np = 0;
-  for (int i = td.pbegin; i < td.pend; i++) {
-    PowerArgs a = probs[order[i]];
-    a.xex = td.xex; a.pex = td.pex; a.vex = td.vex; a.wex = td.wex; a.kscr = td.kscr;
-    a.pw = td.pw; a.xwords = td.xwords; a.vstride = td.vstride;
-    const int err = solve_problem<float, 0, 0>(a, b, td.size, smem, epoch, nx, np);
-    // a timed-out wait leaves this workgroup's exchange counters out of step
-    // with its team: stop here (the team's other members time out in turn)
-    if (err == ERR_SPIN) return;
+  __shared__ int s_h, s_rank;
+  while (true) {
+    if (threadIdx.x == 0) {
+      int h = -1, rank = 0;
+      while (true) {
+        const int cur = __hip_atomic_load(sched, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (cur >= nprob) break;
+        const int seat = atomicAdd(sched + 1 + cur, 1);
+        if (seat < gsize[cur]) { h = cur; rank = seat; break; }
+        atomicCAS(sched, cur, cur + 1);  // full: move the head on (idempotent)
+      }
+      // wait until the team is complete (members may still be finishing an
+      // earlier problem)
+      if (h >= 0) {
+        int64_t budget = join_spin;
+        while (__hip_atomic_load(sched + 1 + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gsize[h]) {
+          if (--budget <= 0) { rank = -1; break; }
+          __builtin_amdgcn_s_sleep(8);
+        }
+      }
+      s_h = h;
+      s_rank = rank;
+    }
+    __syncthreads();
+    const int h = s_h, rank = s_rank;
+    __syncthreads();
+    if (h < 0) return;
+    const PowerArgs a = probs[order[h]];
+    if (rank < 0) {  // the team never assembled: report and leave the problem
+      if (threadIdx.x == 0) atomicMax(a.status + 2, (int)ERR_SPIN);
+      continue;
+    }
+    uint32_t epoch = 0, nx = 0, np = 0;
+    solve_problem<float, 0, 0>(a, rank, gsize[h], smem, epoch, nx, np);
     __syncthreads();
   }
 }
@@ -717,20 +780,20 @@ int power_launch(int is_f64, const PowerPlan& p, PowerArgs a, hipStream_t stream
   return 0;
 }
 
-int power_team_launch(const PowerArgs* d_probs, const int* d_order, const PowerTeam* d_teams,
-                      const int* d_team_of_block, int grid, size_t lds_bytes, uint64_t* zero_base, size_t zero_words,
-                      hipStream_t stream) {
-  if (grid <= 0) return 0;
+int power_dyn_launch(const PowerArgs* d_probs, const int* d_order, const int* d_gsize, int nprob, int* d_sched,
+                     int grid, size_t lds_bytes, uint64_t* zero_base, size_t zero_words, hipStream_t stream) {
+  if (grid <= 0 || nprob <= 0) return 0;
   if (zero_words) {
     hipLaunchKernelGGL(zero_words_kernel, dim3(256), dim3(256), 0, stream, zero_base, zero_words);
     TSVD_HIP_TRY(hipGetLastError());
   }
-  const void* fn = (const void*)power_team_kernel;
+  const void* fn = (const void*)power_dyn_kernel;
   TSVD_HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
   int per_cu = 0;
   TSVD_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, lds_bytes));
   if (per_cu < 1) return -2;
-  void* args[] = {(void*)&d_probs, (void*)&d_order, (void*)&d_teams, (void*)&d_team_of_block};
+  int64_t join_spin = (int64_t)1 << 30;
+  void* args[] = {(void*)&d_probs, (void*)&d_order, (void*)&d_gsize, (void*)&nprob, (void*)&d_sched, (void*)&join_spin};
   TSVD_HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(grid), dim3(256), args, lds_bytes, stream));
   return 0;
 }

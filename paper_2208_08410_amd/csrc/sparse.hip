@@ -140,13 +140,34 @@ __global__ void csc_sort_kernel(const int64_t* colptr, int64_t n, int32_t* rowid
 template <int G, typename XT>
 __global__ __launch_bounds__(256) void spmv_kernel(const int64_t* ptr, const int32_t* idx, const float* val,
                                                    const XT* x, int64_t rows, double* y, float* yf) {
+  // Lane sub of a G-lane group handles entries a + sub, a + sub + G, ... of
+  // its row (in that order, so the FP64 sum is the same for any U).  U of
+  // them are loaded at once: the index and value streams with non-temporal
+  // loads (read once; this keeps the caches for x), then U independent gathers
+  // of x are in flight together.
+  constexpr int U = 4;
   const int sub = threadIdx.x % G;
   const int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
   const int64_t ngrp = ((int64_t)gridDim.x * blockDim.x) / G;
   for (int64_t r = grp; r < rows; r += ngrp) {
     const int64_t a = ptr[r], b = ptr[r + 1];
     double acc = 0.0;
-    for (int64_t e = a + sub; e < b; e += G) acc = fma((double)val[e], (double)x[idx[e]], acc);
+    for (int64_t e0 = a + sub; e0 < b; e0 += (int64_t)G * U) {
+      int32_t ci[U];
+      float vv[U];
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        const int64_t e = e0 + (int64_t)u * G;
+        ci[u] = e < b ? __builtin_nontemporal_load(idx + e) : 0;
+        vv[u] = e < b ? __builtin_nontemporal_load(val + e) : 0.0f;
+      }
+      XT xg[U];
+#pragma unroll
+      for (int u = 0; u < U; u++) xg[u] = e0 + (int64_t)u * G < b ? x[ci[u]] : (XT)0;
+#pragma unroll
+      for (int u = 0; u < U; u++)
+        if (e0 + (int64_t)u * G < b) acc = fma((double)vv[u], (double)xg[u], acc);
+    }
 #pragma unroll
     for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
     if (sub == 0) {
@@ -263,6 +284,18 @@ int csr_validate(const int64_t* rowptr, const int32_t* col, int64_t m, int64_t n
 size_t csc_build_scratch_bytes(int64_t n) {
   const int64_t nb = (n + SCAN_B - 1) / SCAN_B;
   return (size_t)(n + 1) * 8 * 2 + (size_t)(nb + 1) * 8 + 1024;
+}
+
+int scan_counts(const unsigned long long* cnt, int64_t n, unsigned long long* bsum, int64_t* out, int64_t total,
+                hipStream_t s) {
+  const int64_t nb = (n + SCAN_B - 1) / SCAN_B;
+  if (nb > 0) {
+    hipLaunchKernelGGL(scan_block_sums_kernel, dim3((unsigned)nb), dim3(256), 0, s, cnt, n, bsum);
+    hipLaunchKernelGGL(scan_bsums_kernel, dim3(1), dim3(64), 0, s, bsum, nb);
+    hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)nb), dim3(256), 0, s, cnt, n, bsum, out, total);
+  }
+  TSVD_HIP_TRY(hipGetLastError());
+  return 0;
 }
 
 int csc_build(const int64_t* rowptr, const int32_t* col, const float* val, int64_t m, int64_t n, int64_t nnz,

@@ -34,8 +34,8 @@ def tuned(ctx):
 def test_batched_mix_trajectory_vs_oracle(tuned, team_kib):
     """Each problem of a mixed batch follows the FP64 oracle's trajectory
     (fixed iteration counts): vectors within 1e-4 rad, sigma within 1e-6.
-    team_kib 8 puts every problem on one full-chip team (run one after the
-    other), 65536 gives one-workgroup teams, 0 the default split."""
+    team_kib 8 gives every problem the largest team it can use (up to the
+    whole chip), 65536 one-workgroup teams, 0 the default rule."""
     ctx = tuned
     P.set_tuning(ctx, team_kib=team_kib)
     probs, refs = [], []

@@ -111,5 +111,8 @@ def test_tuning_rejects_bad_values(ctx):
         P.set_tuning(ctx, team_kib=4)
     with pytest.raises(P.TsvdError):
         P.set_tuning(ctx, group_kchunk=16)
-    assert P.get_tuning(ctx) == {"gram_tile": 0, "gram_chunks": 0, "power_blocks": 0, "team_kib": 0,
-                                 "group_kchunk": 0}
+    with pytest.raises(P.TsvdError):
+        P.set_tuning(ctx, sparse_row_bits=14)
+    with pytest.raises(P.TsvdError):
+        P.set_tuning(ctx, sparse_row_bits=13, sparse_col_bits=20)
+    assert P.get_tuning(ctx) == {f: 0 for f in P.TUNING_FIELDS}

@@ -50,6 +50,60 @@ def test_spmv_matches_fp64(ctx, trans, xdt):
     assert np.allclose(y, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
 
 
+def awkward_csr(m=500, n=700, seed=11):
+    """Random entries plus the cases the sliced tiles must get right: a full
+    row (many entries of one row in every tile), a long column, empty rows,
+    an empty band of columns, repeated column indices inside a row, and rows
+    whose columns are not sorted."""
+    rng = np.random.default_rng(seed)
+    rows = []
+    for r in range(m):
+        if r % 37 == 0:
+            rows.append(np.array([], dtype=np.int64))  # empty row
+        elif r == 7:
+            rows.append(rng.permutation(n))  # full row, unsorted
+        else:
+            k = rng.poisson(0.03 * n)
+            cols = rng.integers(0, n, k)
+            cols = cols[(cols < 128) | (cols >= 192)]  # no entries in columns 128..191
+            if r % 11 == 0 and len(cols):
+                cols = np.concatenate([cols, cols[:2]])  # repeats
+            if r % 3 == 0:
+                cols = np.concatenate([cols, [300]])  # a long column
+            rows.append(cols)
+    rp = np.zeros(m + 1, dtype=np.int64)
+    rp[1:] = np.cumsum([len(c) for c in rows])
+    ci = np.concatenate(rows).astype(np.int32)
+    va = rng.standard_normal(len(ci)).astype(np.float32)
+    # scipy sums repeated entries, as the CSR definition does
+    M = sp.csr_matrix((va.astype(np.float64), ci, rp), shape=(m, n))
+    return rp, ci, va, M
+
+
+@pytest.mark.parametrize("bits", [(4, 6), (1, 1), (0, 0), (13, 19)])
+def test_tiled_products_awkward_matrix(ctx, bits):
+    """Both products of the sliced-tile kernels (tiny tiles put one row's
+    entries across many tiles and many 64-entry chunks) against FP64 SciPy;
+    products are exact in FP64, so only summation order can differ; two runs
+    give the same bits."""
+    P.set_tuning(ctx, sparse_row_bits=bits[0], sparse_col_bits=bits[1])
+    try:
+        rp, ci, va, M = awkward_csr()
+        c = register(ctx, rp, ci, va, M.shape)
+    finally:
+        P.set_tuning(ctx)
+    for trans in (0, 1):
+        nin = M.shape[1] if trans == 0 else M.shape[0]
+        for xdt in (np.float32, np.float64):
+            x = synth.start_vectors(1, nin, seed=5 + trans)[0].astype(xdt)
+            y = P.tsvd_spmv(ctx, c, to_dev(x), trans=trans).cpu().numpy()
+            y2 = P.tsvd_spmv(ctx, c, to_dev(x), trans=trans).cpu().numpy()
+            ref = (M @ x.astype(np.float64)) if trans == 0 else (M.T @ x.astype(np.float64))
+            absref = (abs(M) @ np.abs(x.astype(np.float64))) if trans == 0 else (abs(M).T @ np.abs(x.astype(np.float64)))
+            assert np.all(np.abs(y - ref) <= 1e-13 * absref + 1e-300), (bits, trans, xdt)
+            assert np.array_equal(y, y2)
+
+
 def test_invalid_csr_rejected(ctx):
     import torch
     rp, ci, va, M = make(100, 80, 0.05, seed=1)
