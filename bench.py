@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--sparse-density", type=float, default=1e-6)
     ap.add_argument("--sparse-k", type=int, default=16)
     ap.add_argument("--sparse-iters", type=int, default=100, help="sparse: fixed iterations per triplet")
+    ap.add_argument("--sparse-row-bits", type=int, default=0, help="sparse: tile rows 2^bits (0 = library)")
+    ap.add_argument("--sparse-col-bits", type=int, default=0, help="sparse: tile columns 2^bits (0 = library)")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: mean arrivals per second")
     ap.add_argument("--window", type=float, default=20.0, help="serve: seconds of measured arrivals")
     ap.add_argument("--warm", type=float, default=2.0, help="serve: seconds of arrivals before the window")
@@ -408,6 +410,8 @@ def sparse_main(a):
     gen_s = time.time() - t0
     nnz = col.numel()
     ctx = P.Context(0)
+    if a.sparse_row_bits or a.sparse_col_bits:
+        P.set_tuning(ctx, sparse_row_bits=a.sparse_row_bits, sparse_col_bits=a.sparse_col_bits)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     progress(f"{nnz} nonzeros; building the CSC copy")
     e0.record()
@@ -456,7 +460,7 @@ def sparse_main(a):
         "dtype": "f32 values, f64 accumulation", "data": "synthetic",
         "config": {"workload": f"sparse CSR {n}x{n}, density {a.sparse_density:g} ({nnz} nnz), uniform random "
                                f"columns, N(0,1) values; k={k}, {a.sparse_iters} fixed iterations per triplet",
-                   "n": n, "nnz": nnz, "k": k},
+                   "n": n, "nnz": nnz, "k": k, "tile_bits": [a.sparse_row_bits, a.sparse_col_bits]},
         "roofline": {"bound": "hbm", "achieved": rates["csr"]["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": rates["csr"]["gbs"] / HBM_PEAK_GBS, "traffic": None, "kernel": "spmv_tiles_kernel (A x)"},
         "spmv": rates,

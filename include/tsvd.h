@@ -134,7 +134,7 @@ typedef struct {
   int32_t sparse_row_bits; /* sparse products: tiles of 2^bits rows (0 = library choice, about 2 row
                               chunks per CU, 32..8192 rows); range [0, 13]; applies to handles created
                               after the call */
-  int32_t sparse_col_bits; /* sparse products: column slices of 2^bits (0 = 2^19: 2 MiB of FP32 x);
+  int32_t sparse_col_bits; /* sparse products: column slices of 2^bits (0 = 2^18: 1 MiB of FP32 x);
                               row + column bits <= 32 */
   int32_t reserved;
 } tsvd_tuning;

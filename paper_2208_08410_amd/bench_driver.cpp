@@ -1,8 +1,10 @@
 // Stand-alone driver for profiling the dense t-SVD through the C ABI, without
 // Python in the process (rocprofv3 runs it directly).
 //
-//   tsvd_bench [m n k eps gram steps warmup seed]
-//     gram: 1 = FP32, 2 = BF16X3
+//   tsvd_bench [m n k eps gram steps warmup seed copy_bytes]
+//     gram: 1 = FP32, 2 = BF16X3; copy_bytes > 0 first runs the copy kernel
+//     below once on that many bytes (a traffic-counter reference in the same
+//     profiled process)
 //   tsvd_bench copy BYTES [reps]
 //     a plain device-to-device copy kernel of BYTES (multiple of 16), the
 //     reference for scaling hardware traffic counters to bytes
@@ -74,6 +76,8 @@ int main(int argc, char** argv) {
   const int steps = argc > 6 ? atoi(argv[6]) : 3;
   const int warmup = argc > 7 ? atoi(argv[7]) : 1;
   const uint64_t seed = argc > 8 ? strtoull(argv[8], nullptr, 10) : 7;
+  const size_t copy_bytes = argc > 9 ? strtoull(argv[9], nullptr, 10) : 0;
+  if (copy_bytes > 0 && run_copy(copy_bytes, 1) != 0) return 1;
   if (m < n || k > n) { fprintf(stderr, "need m >= n >= k\n"); return 2; }
 
   // A = H_L [diag(s); 0] H_R, built row by row: row i of [diag(s); 0] H_R is

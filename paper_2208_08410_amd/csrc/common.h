@@ -86,11 +86,93 @@ __device__ __forceinline__ bool ll_read_words(const uint64_t* p, int64_t count, 
 // Deterministic reductions (fixed association order, result taken from lane 0)
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, kWave);
-  return v;  // valid in lane 0
+// ---------------------------------------------------------------------------
+// Cross-lane reductions on DPP (data-parallel primitives: a lane reads another
+// lane's register inside the VALU instruction), which are much cheaper than
+// shuffles through the LDS permute unit.  A double moves as two 32-bit halves.
+// Controls (GFX9 family): 0x4E quad_perm [2,3,0,1], 0xB1 quad_perm [1,0,3,2],
+// 0x111 + s row_shr:s, 0x130 wave_shl:1, 0x140 row_mirror, 0x141
+// row_half_mirror, 0x142 row_bcast:15, 0x143 row_bcast:31.
+// ---------------------------------------------------------------------------
+template <int CTRL, int ROW_MASK, bool BOUND_ZERO>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const int tlo = __builtin_amdgcn_update_dpp(0, lo, CTRL, ROW_MASK, 0xF, BOUND_ZERO);
+  const int thi = __builtin_amdgcn_update_dpp(0, hi, CTRL, ROW_MASK, 0xF, BOUND_ZERO);
+  return __hiloint2double(thi, tlo);
 }
+template <int CTRL, int ROW_MASK, bool BOUND_ZERO>
+__device__ __forceinline__ int dpp_i32(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, ROW_MASK, 0xF, BOUND_ZERO);
+}
+// the key of another lane, with "no lane" (out of row, or a row left out of
+// ROW_MASK) reading as -1: keys travel as key + 1 so that 0 means "none"
+template <int CTRL, int ROW_MASK, bool BOUND_ZERO>
+__device__ __forceinline__ int dpp_key(int key) {
+  return (int)((unsigned)dpp_i32<CTRL, ROW_MASK, BOUND_ZERO>((int)((unsigned)key + 1u)) - 1u);
+}
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes in a fixed order (pairs, quads, 8, 16, then rows);
+// every lane returns the total.
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_f64<0xB1, 0xF, false>(v);   // lane ^ 1
+  v += dpp_f64<0x4E, 0xF, false>(v);   // lane ^ 2
+  v += dpp_f64<0x141, 0xF, false>(v);  // mirror within 8: other quad
+  v += dpp_f64<0x140, 0xF, false>(v);  // mirror within 16: other half row
+  v += dpp_f64<0x142, 0xA, false>(v);  // row 1 += row 0, row 3 += row 2
+  v += dpp_f64<0x143, 0xC, false>(v);  // rows 2, 3 += lane 31 (rows 0 + 1)
+  return readlane_f64(v, 63);
+}
+
+// Inclusive scan of p over lanes, restarted wherever key changes; keys must be
+// non-decreasing over the lanes (equal keys contiguous).  Lane i receives the
+// sum of p over the lanes j <= i with key[j] == key[i].
+__device__ __forceinline__ double wave_seg_scan(double p, int key) {
+  // within rows of 16: Hillis-Steele with shifts 1, 2, 4, 8 (lanes shifted in
+  // from before the row start read 0 / key -1, which never matches)
+  {
+    const double t = dpp_f64<0x111, 0xF, true>(p);
+    const int k = dpp_key<0x111, 0xF, true>(key);
+    if (k == key) p += t;
+  }
+  {
+    const double t = dpp_f64<0x112, 0xF, true>(p);
+    const int k = dpp_key<0x112, 0xF, true>(key);
+    if (k == key) p += t;
+  }
+  {
+    const double t = dpp_f64<0x114, 0xF, true>(p);
+    const int k = dpp_key<0x114, 0xF, true>(key);
+    if (k == key) p += t;
+  }
+  {
+    const double t = dpp_f64<0x118, 0xF, true>(p);
+    const int k = dpp_key<0x118, 0xF, true>(key);
+    if (k == key) p += t;
+  }
+  // across rows: a segment that reaches a row's start continues the previous
+  // row's last lane (keys are sorted, so equal keys mean the lanes between
+  // all belong to that segment)
+  {
+    const double t = dpp_f64<0x142, 0xA, false>(p);
+    const int k = dpp_key<0x142, 0xA, false>(key);
+    if (((threadIdx.x >> 4) & 1) && k == key) p += t;
+  }
+  {
+    const double t = dpp_f64<0x143, 0xC, false>(p);
+    const int k = dpp_key<0x143, 0xC, false>(key);
+    if (((threadIdx.x >> 5) & 1) && k == key) p += t;
+  }
+  return p;
+}
+
+// key of lane + 1 (lane 63 reads -1)
+__device__ __forceinline__ int next_lane_key(int key) { return dpp_key<0x130, 0xF, true>(key); }
 
 // Sum of one double per thread over a block of nthr (multiple of 64) threads;
 // red must hold nthr/64 doubles.  Every thread returns the same value.

@@ -118,8 +118,6 @@ int csr_validate(const int64_t* rowptr, const int32_t* col, int64_t m, int64_t n
 size_t csc_build_scratch_bytes(int64_t n);
 int csc_build(const int64_t* rowptr, const int32_t* col, const float* val, int64_t m, int64_t n, int64_t nnz,
               int64_t* colptr, int32_t* rowidx, float* cval, void* scratch, hipStream_t s);
-int spmv_launch(const int64_t* ptr, const int32_t* idx, const float* val, const void* x, int x_is_f64, int64_t rows,
-                int64_t nnz, double* y, float* yf, hipStream_t s);
 // exclusive scan of n counts into out[0..n] (out[n] = total); bsum: (n + 1023) / 1024 + 1 entries
 int scan_counts(const unsigned long long* cnt, int64_t n, unsigned long long* bsum, int64_t* out, int64_t total,
                 hipStream_t s);

@@ -10,8 +10,6 @@
 //   csc_count/scan/fill   builds the CSC copy (counting sort by column);
 //   csc_sort_kernel       orders rows inside each column so sums are
 //                         deterministic
-//   spmv_kernel<G, XT>    y = A x for a compressed-row structure: G lanes per
-//                         row, FP32 values, x gathered as XT, FP64 accumulation
 //   proj_partials_kernel  block partials of V^T w, ||w||^2 and x . w
 //   proj_apply_kernel     z = w - V c, partial ||z||^2
 //   normalize_kernel      x = z / ||z|| (FP64) and its FP32 copy
@@ -129,50 +127,6 @@ __global__ void csc_sort_kernel(const int64_t* colptr, int64_t n, int32_t* rowid
       }
       rowidx[j + 1] = r;
       cval[j + 1] = v;
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// SpMV: y[i] = sum_e val[e] * x[idx[e]] over e in [ptr[i], ptr[i+1])
-// G lanes cooperate on one row; a 256-thread block covers 256/G rows per pass.
-// ---------------------------------------------------------------------------
-template <int G, typename XT>
-__global__ __launch_bounds__(256) void spmv_kernel(const int64_t* ptr, const int32_t* idx, const float* val,
-                                                   const XT* x, int64_t rows, double* y, float* yf) {
-  // Lane sub of a G-lane group handles entries a + sub, a + sub + G, ... of
-  // its row (in that order, so the FP64 sum is the same for any U).  U of
-  // them are loaded at once: the index and value streams with non-temporal
-  // loads (read once; this keeps the caches for x), then U independent gathers
-  // of x are in flight together.
-  constexpr int U = 4;
-  const int sub = threadIdx.x % G;
-  const int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
-  const int64_t ngrp = ((int64_t)gridDim.x * blockDim.x) / G;
-  for (int64_t r = grp; r < rows; r += ngrp) {
-    const int64_t a = ptr[r], b = ptr[r + 1];
-    double acc = 0.0;
-    for (int64_t e0 = a + sub; e0 < b; e0 += (int64_t)G * U) {
-      int32_t ci[U];
-      float vv[U];
-#pragma unroll
-      for (int u = 0; u < U; u++) {
-        const int64_t e = e0 + (int64_t)u * G;
-        ci[u] = e < b ? __builtin_nontemporal_load(idx + e) : 0;
-        vv[u] = e < b ? __builtin_nontemporal_load(val + e) : 0.0f;
-      }
-      XT xg[U];
-#pragma unroll
-      for (int u = 0; u < U; u++) xg[u] = e0 + (int64_t)u * G < b ? x[ci[u]] : (XT)0;
-#pragma unroll
-      for (int u = 0; u < U; u++)
-        if (e0 + (int64_t)u * G < b) acc = fma((double)vv[u], (double)xg[u], acc);
-    }
-#pragma unroll
-    for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
-    if (sub == 0) {
-      if (y) y[r] = acc;
-      if (yf) yf[r] = (float)acc;
     }
   }
 }
@@ -312,27 +266,6 @@ int csc_build(const int64_t* rowptr, const int32_t* col, const float* val, int64
   hipLaunchKernelGGL(csc_fill_kernel, dim3(grid_for(m * 64, 256, 65536)), dim3(256), 0, s, rowptr, col, val, m,
                      colptr, fill, rowidx, cval);
   hipLaunchKernelGGL(csc_sort_kernel, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, colptr, n, rowidx, cval);
-  TSVD_HIP_TRY(hipGetLastError());
-  return 0;
-}
-
-int spmv_launch(const int64_t* ptr, const int32_t* idx, const float* val, const void* x, int x_is_f64, int64_t rows,
-                int64_t nnz, double* y, float* yf, hipStream_t s) {
-  const double avg = rows > 0 ? (double)nnz / (double)rows : 0.0;
-  const int grid = grid_for(rows * 16, 256, 1 << 22);
-  if (x_is_f64) {
-    if (avg > 96) hipLaunchKernelGGL((spmv_kernel<64, double>), dim3(grid_for(rows * 64, 256, 1 << 22)), dim3(256), 0,
-                                     s, ptr, idx, val, (const double*)x, rows, y, yf);
-    else hipLaunchKernelGGL((spmv_kernel<16, double>), dim3(grid), dim3(256), 0, s, ptr, idx, val, (const double*)x,
-                            rows, y, yf);
-  } else {
-    if (avg > 96) hipLaunchKernelGGL((spmv_kernel<64, float>), dim3(grid_for(rows * 64, 256, 1 << 22)), dim3(256), 0,
-                                     s, ptr, idx, val, (const float*)x, rows, y, yf);
-    else if (avg > 24) hipLaunchKernelGGL((spmv_kernel<16, float>), dim3(grid), dim3(256), 0, s, ptr, idx, val,
-                                          (const float*)x, rows, y, yf);
-    else hipLaunchKernelGGL((spmv_kernel<8, float>), dim3(grid_for(rows * 8, 256, 1 << 22)), dim3(256), 0, s, ptr,
-                            idx, val, (const float*)x, rows, y, yf);
-  }
   TSVD_HIP_TRY(hipGetLastError());
   return 0;
 }

@@ -9,14 +9,14 @@
 //
 // y = A x then runs one workgroup per row chunk, accumulating the chunk's y in
 // LDS (FP64) while it walks the slices in order.  All workgroups walk the
-// slices in the same order, so at any time the x gathers of the chip hit one
-// or two 2 MiB slices that sit in L2, instead of a 200 MB vector scattered
+// slices in the same order, so at any time the x gathers of the chip hit a
+// few 1 MiB slices that sit in L2, instead of a 200 MB vector scattered
 // over HBM: random gathers that miss L2 run at a fraction of the rate of those
 // that hit it.  Keys and values are streamed once with non-temporal loads.
 //
 // Products are exact in FP64; the sums use a fixed order (a segmented scan
-// over 64 lanes, then per-wave boundary rows added by one thread in wave
-// order), so results are deterministic.
+// over 64 lanes on DPP, then per-wave boundary rows added by one thread in
+// wave order), so results are deterministic.
 #include "common.h"
 #include "internal.h"
 
@@ -119,63 +119,55 @@ __global__ __launch_bounds__(TW * 64) void spmv_tiles_kernel(const int64_t* tptr
     int carry_row = -1;  // wave-uniform: the open segment at the end of the last chunk
     double carry = 0.0;
     double left = 0.0;   // the first segment's sum, held by the one lane that closed it
-    // two-stage software pipeline: the keys and values of chunk i + 1 are
-    // loaded and the x entries of chunk i + 1 are gathered while chunk i is
-    // reduced, so each wave keeps several memory requests in flight
-    uint32_t kA = 0, kB = 0;
-    float vA = 0.f, vB = 0.f;
-    XT xA = (XT)0;
-    if (wa + lane < wb) {
-      kA = __builtin_nontemporal_load(key + wa + lane);
-      vA = __builtin_nontemporal_load(val + wa + lane);
-    }
-    if (wa + 64 + lane < wb) {
-      kB = __builtin_nontemporal_load(key + wa + 64 + lane);
-      vB = __builtin_nontemporal_load(val + wa + 64 + lane);
-    }
-    if (wa + lane < wb) xA = xs[kA & cmask];
-    for (int64_t e0 = wa; e0 < wb; e0 += 64) {
-      const int64_t e = e0 + lane;
-      const bool valid = e < wb;
-      const int nvalid = (int)min((int64_t)64, wb - e0);
-      int row = 0x7fffffff;
-      double p = 0.0;
-      if (valid) {
-        row = (int)(kA >> cbits);
-        p = (double)vA * (double)xA;
-      }
-      // advance the pipeline
-      kA = kB;
-      vA = vB;
-      if (e + 64 < wb) xA = xs[kA & cmask];
-      if (e + 128 < wb) {
-        kB = __builtin_nontemporal_load(key + e + 128);
-        vB = __builtin_nontemporal_load(val + e + 128);
-      }
-      // the open segment ended exactly at the last chunk's end: close it
-      if (carry_row >= 0 && __shfl(row, 0, 64) != carry_row) {
-        if (lane == 0) {
-          if (carry_row == first_row) left = carry;
-          else yl[carry_row] += carry;  // interior row: no other wave holds it
-        }
-        carry_row = -1;
-        carry = 0.0;
-      }
-      // segmented inclusive scan (rows are sorted, so equal rows are contiguous)
+    // UC chunks of 64 entries per step: their keys, values and x gathers are
+    // all issued before the first scan, so each wave keeps UC independent
+    // gathers in flight; the chunks are then reduced in order
+    constexpr int UC = 4;
+    for (int64_t s0 = wa; s0 < wb; s0 += 64 * UC) {
+      uint32_t kk[UC];
+      float vv[UC];
+      XT xx[UC];
 #pragma unroll
-      for (int off = 1; off < 64; off <<= 1) {
-        const double q = __shfl_up(p, off, 64);
-        const int rq = __shfl_up(row, off, 64);
-        if (lane >= off && rq == row) p += q;
+      for (int u = 0; u < UC; u++) {
+        const int64_t e = s0 + 64 * u + lane;
+        kk[u] = e < wb ? __builtin_nontemporal_load(key + e) : 0u;
+        vv[u] = e < wb ? __builtin_nontemporal_load(val + e) : 0.f;
       }
-      if (row == carry_row) p += carry;  // the segment continued from the last chunk
-      const int rn = __shfl_down(row, 1, 64);
-      if (valid && lane < nvalid - 1 && rn != row) {  // a segment ends inside this chunk
-        if (row == first_row) left = p;  // only the first segment has first_row
-        else yl[row] += p;
+#pragma unroll
+      for (int u = 0; u < UC; u++) xx[u] = (s0 + 64 * u + lane < wb) ? xs[kk[u] & cmask] : (XT)0;
+#pragma unroll
+      for (int u = 0; u < UC; u++) {
+        const int64_t e0 = s0 + 64 * u;
+        if (e0 >= wb) break;  // uniform
+        const int64_t e = e0 + lane;
+        const bool valid = e < wb;
+        const int nvalid = (int)min((int64_t)64, wb - e0);
+        int row = 0x7fffffff;
+        double p = 0.0;
+        if (valid) {
+          row = (int)(kk[u] >> cbits);
+          p = (double)vv[u] * (double)xx[u];
+        }
+        // the open segment ended exactly at the last chunk's end: close it
+        if (carry_row >= 0 && __builtin_amdgcn_readlane(row, 0) != carry_row) {
+          if (lane == 0) {
+            if (carry_row == first_row) left = carry;
+            else yl[carry_row] += carry;  // interior row: no other wave holds it
+          }
+          carry_row = -1;
+          carry = 0.0;
+        }
+        // segmented inclusive scan (rows are sorted, so equal rows are contiguous)
+        p = wave_seg_scan(p, row);
+        if (row == carry_row) p += carry;  // the segment continued from the last chunk
+        const int rn = next_lane_key(row);
+        if (valid && lane < nvalid - 1 && rn != row) {  // a segment ends inside this chunk
+          if (row == first_row) left = p;  // only the first segment has first_row
+          else yl[row] += p;
+        }
+        carry_row = __builtin_amdgcn_readlane(row, nvalid - 1);
+        carry = readlane_f64(p, nvalid - 1);
       }
-      carry_row = __shfl(row, nvalid - 1, 64);
-      carry = __shfl(p, nvalid - 1, 64);
     }
     // boundary rows: the first segment (left) and the open last one (right);
     // they are added by one thread in wave order after the tile
@@ -216,7 +208,7 @@ int tiles_plan(int64_t rows, int64_t cols, int num_cu, int rbits_hint, int cbits
     rb = 13;
     while (rb > 5 && (rows >> rb) < 2 * (int64_t)num_cu) rb--;
   }
-  int cb = cbits_hint > 0 ? cbits_hint : 19;  // 2 MiB FP32 slices of x
+  int cb = cbits_hint > 0 ? cbits_hint : 18;  // 1 MiB FP32 slices of x (measured best of 2^18 / 2^19)
   const int lc = ceil_log2(cols);
   if (cb > lc) cb = lc > 0 ? lc : 1;
   if (cb < lc - 14) cb = lc - 14;  // at most 16384 slices (tile_count_kernel's LDS histogram)
