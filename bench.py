@@ -76,6 +76,34 @@ def parse():
     return ap.parse_args()
 
 
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE, WRITE_SIZE scaled by a reference copy), or None when
+    the kernel's device source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_power_gram_finish_dense_200000x4096_k64.txt")
+    csrc = os.path.join(ROOT, "paper_2208_08410_amd", "csrc")
+    try:
+        lines = open(path).read().splitlines()
+        power = open(os.path.join(csrc, "power.hip")).read()
+        common = open(os.path.join(csrc, "common.h")).read()
+    except OSError:
+        return None
+    now = {"power.hip-device": hashlib.sha256(power[:power.index("// Host side")].encode()).hexdigest()[:16],
+           "common.h": hashlib.sha256(common.encode()).hexdigest()[:16]}
+    for l in lines:
+        if l.startswith("sha256-16 "):
+            _, name, h = l.split()
+            if now.get(name) != h:
+                return None
+    for l in lines:
+        if l.startswith("kernel " + kernel + " "):
+            f = dict(kv.split("=") for kv in l.split()[2:])
+            return float(f["fetch_kib"]) * 1024 * float(f["fetch_scale"]) + \
+                float(f["write_kib"]) * 1024 * float(f["write_scale"])
+    return None
+
+
 def power_bytes_per_launch(iters, k, n, elem=4):
     """Algorithmic bytes of the power-iteration launch: every iteration reads B
     (n^2 elements) once; every triplet but the last adds one more product with
@@ -242,12 +270,18 @@ def serve_main(a):
         results.append((t_arr, info, rel, k, tuple(A.shape)))
     t_end = time.perf_counter() - t_start
     st = srv.stats()
+    server_error = srv.last_error()
     srv.close()
     ctx.close()
     meas = [x for x in results if x[0] >= a.warm]
     lat = np.array([x[1]["latency_ms"] for x in meas])
     ok = all(x[1]["status"] == "TSVD_OK" for x in results)
-    errs = np.array([x[2] for x in meas])
+    statuses = {}
+    for x in results:
+        statuses[x[1]["status"]] = statuses.get(x[1]["status"], 0) + 1
+    failed = [{"shape": x[4], "k": x[3], "status": x[1]["status"], "k_done": x[1]["k_done"]}
+              for x in results if x[1]["status"] != "TSVD_OK"][:10]
+    errs = np.array([x[2] for x in meas if x[1]["status"] == "TSVD_OK"] or [float("nan")])
     out = {
         "metric": METRIC,
         "value": float(np.percentile(lat, 99)),
@@ -274,6 +308,9 @@ def serve_main(a):
         "offered_rate": a.rate,
         "achieved_rate": len(results) / t_end,
         "all_ok": ok,
+        "statuses": statuses,
+        "failed_examples": failed,
+        "server_error": server_error,
         "sigma_rel_err_max": float(errs.max()),
         "meets_1e-6": bool(errs.max() < 1e-6),
         "batches": st["batches"],
@@ -551,14 +588,17 @@ def main():
         "traffic": None,
         "effective_fp32_equiv_tflops": gram_flops_alg / (t_gram * 1e-3) / 1e12,
     }
+    traffic = measured_traffic("power_kernel<float,16,2>") if a.n == 4096 and a.m == 200000 and a.k == 64 else None
     roof_power = {
-        "kernel": "power_kernel<float>",
+        "kernel": "power_kernel<float,16,2>",
         "bound": "hbm",
         "achieved": pbytes / (t_eig * 1e-3) / 1e9,
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": pbytes / (t_eig * 1e-3) / 1e9 / HBM_PEAK_GBS,
-        "traffic": None,
+        "traffic": traffic,
+        "traffic_note": "HBM bytes per launch from profiles/traffic_*.txt (rocprofv3 FETCH_SIZE/WRITE_SIZE, scaled "
+                        "by a reference copy); far below the algorithmic bytes because B stays on chip",
         "units_per_launch": punits,
         "bytes_per_unit": a.n * a.n * 4,
         "us_per_iteration": t_eig * 1e3 / max(1, sum(info["iters"])),

@@ -587,6 +587,9 @@ class Server:
         st = self.ctx.lib.tsvd_server_wait(self.handle, ticket, ctypes.byref(info))
         return self._result(ticket, info, st)
 
+    def last_error(self) -> str:
+        return self.ctx.lib.tsvd_server_last_error(self.handle).decode()
+
     def stats(self) -> dict:
         s = TsvdServerStats()
         self.ctx.check(self.ctx.lib.tsvd_server_get_stats(self.handle, ctypes.byref(s)))

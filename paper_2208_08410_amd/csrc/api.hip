@@ -24,6 +24,7 @@ int hip_fail(hipError_t e, const char* what, const char* file, int line) {
   char buf[512];
   snprintf(buf, sizeof buf, "HIP error '%s' (%d) in %s at %s:%d", hipGetErrorString(e), (int)e, what, file, line);
   g_hip_msg = buf;
+  (void)hipGetLastError();  // clear the sticky error so later calls do not report it again
   return TSVD_ERR_HIP;
 }
 

@@ -96,7 +96,8 @@ tsvd_status batch_plan(tsvd_ctx* ctx, int count, const tsvd_problem* probs, Batc
     const int64_t M = p.right ? q.m : q.n;
     p.nb = (int)((M + 127) / 128);
     p.G = wanted_team(p.d, ctx->num_cu, team_kib);
-    if (power_plan(4, (int)p.d, p.k, ctx->num_cu, ctx->max_lds, p.G, &p.pp))
+    // the batched kernel's own static LDS comes out of the per-workgroup budget
+    if (power_plan(4, (int)p.d, p.k, ctx->num_cu, ctx->max_lds - power_dyn_static_lds(), p.G, &p.pp))
       return fail(ctx, TSVD_ERR_UNSUPPORTED, "problem %d: d=%lld too large for the LDS-resident iterate", i,
                   (long long)p.d);
     p.G = p.pp.G;

@@ -76,6 +76,8 @@ int power_launch(int is_f64, const PowerPlan& p, PowerArgs a, hipStream_t stream
 // (queue order) with team sizes gsize[h]; sched holds 1 + n ints, zero on
 // entry; grid workgroups, one per CU (cooperative); zero_words of exchange
 // memory at zero_base are cleared first
+// static LDS of the batched power kernel (its dynamic LDS must leave room for it)
+size_t power_dyn_static_lds();
 int power_dyn_launch(const PowerArgs* d_probs, const int* d_order, const int* d_gsize, int nprob, int* d_sched,
                      int grid, size_t lds_bytes, uint64_t* zero_base, size_t zero_words, hipStream_t stream);
 

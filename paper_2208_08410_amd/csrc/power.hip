@@ -780,6 +780,16 @@ int power_launch(int is_f64, const PowerPlan& p, PowerArgs a, hipStream_t stream
   return 0;
 }
 
+size_t power_dyn_static_lds() {
+  static size_t bytes = (size_t)-1;
+  if (bytes == (size_t)-1) {
+    hipFuncAttributes attr;
+    bytes = hipFuncGetAttributes(&attr, (const void*)power_dyn_kernel) == hipSuccess ? attr.sharedSizeBytes : 256;
+    (void)hipGetLastError();
+  }
+  return bytes;
+}
+
 int power_dyn_launch(const PowerArgs* d_probs, const int* d_order, const int* d_gsize, int nprob, int* d_sched,
                      int grid, size_t lds_bytes, uint64_t* zero_base, size_t zero_words, hipStream_t stream) {
   if (grid <= 0 || nprob <= 0) return 0;

@@ -217,6 +217,7 @@ void admit(tsvd_server* s) {
       if (hipEventCreateWithFlags(&r->copied, hipEventDisableTiming) != hipSuccess ||
           hipMemcpyAsync(r->staged, r->prob.A, bytes, hipMemcpyHostToDevice, s->copy) != hipSuccess ||
           hipEventRecord(r->copied, s->copy) != hipSuccess) {
+        s->error = std::string("staging copy: ") + hipGetErrorString(hipGetLastError());
         s->waiting.pop_front();
         s->in_flight++;
         release_request(s, r);
@@ -325,6 +326,7 @@ void collect(tsvd_server* s) {
       r->info.workspace_bytes = (int64_t)r->footprint;
       r->info.h2d_bytes = r->loc == TSVD_LOC_PINNED_HOST ? (int64_t)(r->prob.m * r->prob.lda * 4) : 0;
     } else {
+      s->error = std::string("batch completion: ") + hipGetErrorString(q);
       (void)hipGetLastError();
     }
     release_request(s, r);

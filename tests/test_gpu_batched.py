@@ -147,3 +147,28 @@ def test_batched_invalid_arguments_and_budget(ctx):
         P.tsvd_dense_batched(ctx, [good], hbm_budget=1 << 12)
     assert e.value.status == P.OUT_OF_MEMORY
     assert P.tsvd_dense_batched(ctx, []) == []
+
+
+@pytest.mark.parametrize("team_kib", [512, 1024])
+def test_batched_random_mix_team_rules(tuned, team_kib):
+    """Forty random shapes per batch under larger team_kib rules (teams read
+    most Gram rows from HBM, and some plans fill a workgroup's LDS to the last
+    row): every problem meets the closed form; two batches in a row on one
+    context both succeed."""
+    ctx = tuned
+    P.set_tuning(ctx, team_kib=team_kib)
+    rng = np.random.default_rng(team_kib)
+    for rep in range(2):
+        probs, dks = [], []
+        for i in range(40):
+            m = int(np.exp(rng.uniform(np.log(256), np.log(4096))))
+            n = int(np.exp(rng.uniform(np.log(64), np.log(1500))))
+            k = int(min(rng.choice([2, 4, 8]), m, n))
+            dk, st = make_problem(m, n, k, "bf16x3", seed=1000 * rep + i, q=0.8)
+            dks.append(dk)
+            probs.append(dict(A=to_dev(dk.A), k=k, eps=1e-12, v0=to_dev(st), gram="bf16x3"))
+        out = P.tsvd_dense_batched(ctx, probs, raise_errors=True)
+        for dk, p, (U, S, V, info) in zip(dks, probs, out):
+            k = p["k"]
+            assert info["status"] == "TSVD_OK"
+            assert np.max(np.abs(S.cpu().numpy() - dk.s[:k]) / dk.s[:k]) < 1e-6
