@@ -51,74 +51,79 @@ __device__ __forceinline__ void load_vec<double>(const double* p, double (&v)[2]
   v[0] = f.x; v[1] = f.y;
 }
 
-// y[li] = B row li . x for rows li in [begin, end) of one storage (LDS or HBM).
-// Rows are dealt to the 4 waves round-robin (wave w: begin + w + 4j); a wave
-// takes 4 of its rows per pass so each x chunk read from LDS feeds 4 rows.
-// The column loop is unrolled UNR times (deeper for rows read from HBM, so
-// that more loads are in flight).  Each lane keeps one accumulator per (row,
-// vector component) in B's type:
-// 16 independent FMA chains for FP32 (one wave per SIMD has no other wave to
-// hide FMA and LDS latency behind), about d / 256 products per chain; the
+// y[r] = scale * (B row r . x) for the NR rows r = first + 4q (q < NR) of one
+// storage (LDS or HBM).  The body is straight-line (every load and FMA is
+// unconditional), so the loads of UNR column steps are in flight together; a
+// per-row predicate inside the loop would make the compiler wait for each LDS
+// load on its own.  Each lane keeps one FMA chain per (row, vector component)
+// in B's type (16 chains for FP32 and 4 rows: one wave per SIMD has no other
+// wave to hide FMA and LDS latency behind), about d / 256 products per chain;
 // chains and lanes are then added in FP64.
-template <typename BT, int UNR = 2>
-__device__ void gemv_range(const BT* rows, int64_t stride, int begin, int end, const BT* xs, int d, bool vec_ok,
-                           double* yout) {
+template <typename BT, int NR, int UNR>
+__device__ __forceinline__ void gemv_rows(const BT* rows, int64_t stride, int first, const BT* xs, int d, int dv,
+                                          double scale, double* yout) {
   constexpr int VN = VecOf<BT>::N;
   using VT = typename std::conditional<sizeof(BT) == 4, float4, double2>::type;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int dv = vec_ok ? (d / VN) * VN : 0;
-  for (int j0 = 0; begin + wave + 4 * j0 < end; j0 += 4) {
-    int li[4];
-    int nr = 0;
+  const int lane = threadIdx.x & 63;
+  const BT* rp[NR];
 #pragma unroll
-    for (int q = 0; q < 4; q++) {
-      li[q] = begin + wave + 4 * (j0 + q);
-      if (li[q] < end) nr = q + 1;
-    }
-    BT acc[4][VN];
+  for (int q = 0; q < NR; q++) rp[q] = rows + (int64_t)(first + 4 * q) * stride;
+  BT acc[NR][VN];
 #pragma unroll
-    for (int q = 0; q < 4; q++)
+  for (int q = 0; q < NR; q++)
 #pragma unroll
-      for (int e = 0; e < VN; e++) acc[q][e] = (BT)0;
-    const BT* rp[4];
-#pragma unroll
-    for (int q = 0; q < 4; q++) rp[q] = rows + (int64_t)(q < nr ? li[q] : li[0]) * stride;
+    for (int e = 0; e < VN; e++) acc[q][e] = (BT)0;
 #pragma unroll UNR
-    for (int c = lane * VN; c < dv; c += 64 * VN) {
-      const VT xv = *(const VT*)(xs + c);
-      VT bv[4];
+  for (int c = lane * VN; c < dv; c += 64 * VN) {
+    const VT xv = *(const VT*)(xs + c);
+    VT bv[NR];
 #pragma unroll
-      for (int q = 0; q < 4; q++)
-        if (q < nr) bv[q] = *(const VT*)(rp[q] + c);
+    for (int q = 0; q < NR; q++) bv[q] = *(const VT*)(rp[q] + c);
 #pragma unroll
-      for (int q = 0; q < 4; q++) {
-        if (q < nr) {
-          if constexpr (VN == 4) {
-            acc[q][0] = fma(bv[q].x, xv.x, acc[q][0]);
-            acc[q][1] = fma(bv[q].y, xv.y, acc[q][1]);
-            acc[q][2] = fma(bv[q].z, xv.z, acc[q][2]);
-            acc[q][3] = fma(bv[q].w, xv.w, acc[q][3]);
-          } else {
-            acc[q][0] = fma(bv[q].x, xv.x, acc[q][0]);
-            acc[q][1] = fma(bv[q].y, xv.y, acc[q][1]);
-          }
-        }
+    for (int q = 0; q < NR; q++) {
+      if constexpr (VN == 4) {
+        acc[q][0] = fma(bv[q].x, xv.x, acc[q][0]);
+        acc[q][1] = fma(bv[q].y, xv.y, acc[q][1]);
+        acc[q][2] = fma(bv[q].z, xv.z, acc[q][2]);
+        acc[q][3] = fma(bv[q].w, xv.w, acc[q][3]);
+      } else {
+        acc[q][0] = fma(bv[q].x, xv.x, acc[q][0]);
+        acc[q][1] = fma(bv[q].y, xv.y, acc[q][1]);
       }
     }
-    for (int c = dv + lane; c < d; c += 64) {
-      const BT xv = xs[c];
+  }
+  for (int c = dv + lane; c < d; c += 64) {
+    const BT xv = xs[c];
 #pragma unroll
-      for (int q = 0; q < 4; q++)
-        if (q < nr) acc[q][0] = fma(rp[q][c], xv, acc[q][0]);
-    }
+    for (int q = 0; q < NR; q++) acc[q][0] = fma(rp[q][c], xv, acc[q][0]);
+  }
 #pragma unroll
-    for (int q = 0; q < 4; q++) {
-      double t = 0.0;
+  for (int q = 0; q < NR; q++) {
+    double t = 0.0;
 #pragma unroll
-      for (int e = 0; e < VN; e++) t += (double)acc[q][e];
-      const double sum = wave_sum(t);
-      if (lane == 0 && q < nr) yout[li[q]] = sum;
-    }
+    for (int e = 0; e < VN; e++) t += (double)acc[q][e];
+    const double sum = wave_sum(t);
+    if (lane == 0) yout[first + 4 * q] = sum * scale;
+  }
+}
+
+// y[li] = scale * (B row li . x) for rows li in [begin, end) of one storage.
+// Rows are dealt to the 4 waves round-robin (wave w: begin + w + 4j); a wave
+// takes up to 4 of its rows per pass so each x chunk read from LDS feeds them
+// all.  The wave index is made explicitly uniform so the row-count dispatch is
+// a scalar branch.
+template <typename BT, int UNR = 2>
+__device__ void gemv_range(const BT* rows, int64_t stride, int begin, int end, const BT* xs, int d, bool vec_ok,
+                           double scale, double* yout) {
+  constexpr int VN = VecOf<BT>::N;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int dv = vec_ok ? (d / VN) * VN : 0;
+  for (int first = begin + wave; first < end; first += 16) {
+    const int nr = (end - first + 3) / 4;
+    if (nr >= 4) gemv_rows<BT, 4, UNR>(rows, stride, first, xs, d, dv, scale, yout);
+    else if (nr == 3) gemv_rows<BT, 3, UNR>(rows, stride, first, xs, d, dv, scale, yout);
+    else if (nr == 2) gemv_rows<BT, 2, UNR>(rows, stride, first, xs, d, dv, scale, yout);
+    else gemv_rows<BT, 1, UNR>(rows, stride, first, xs, d, dv, scale, yout);
   }
 }
 
@@ -132,8 +137,9 @@ struct RegRows {
 
 template <typename BT, int NV, int RR>
 __device__ __forceinline__ void gemv_regrows(const RegRows<BT, NV, RR>& R, int cr, int nreg, const BT* xs,
-                                             double* yout) {
+                                             double scale, double* yout) {
   if constexpr (RR > 0 && NV > 0) {
+    if (nreg <= 0) return;
     // per-lane partial sums in BT (16 products per chain at d = 4096),
     // summed across chains and lanes in FP64
     constexpr int VN = VecOf<BT>::N;
@@ -165,7 +171,7 @@ __device__ __forceinline__ void gemv_regrows(const RegRows<BT, NV, RR>& R, int c
 #pragma unroll
       for (int e = 0; e < VN; e++) t += (double)acc[q][e];
       double sum = wave_sum(t);
-      if (lane == 0 && li < nreg) yout[cr + li] = sum;
+      if (lane == 0 && li < nreg) yout[cr + li] = sum * scale;
     }
   }
 }
@@ -480,31 +486,35 @@ __device__ int solve_problem(const PowerArgs& a, int b, int G, unsigned char* sm
     int it = 0;
     double nrm = 0.0;
     bool conv = false;
+    // x_t = scale * xs: xs holds x_0, then the gathered y_t as published; the
+    // normalisation 1 / ||y_t|| is applied to the next product's row sums
+    // instead of to the iterate (the same value without a pass over xs)
+    double scale = 1.0;
     // register rows live only for this triplet's iterations: loaded from B here,
     // written back before the deflation (which updates them in B)
     RegRows<BT, NV, RR> R;
     load_regrows<BT, NV, RR>(R, Bg, a.ldb, cr, nreg, d);
     while (true) {
       // ---- y = B x on the block's rows
-      gemv_regrows<BT, NV, RR>(R, cr, nreg, xs, yv);
-      gemv_range<BT>(Bs, a.ldsB, 0, cr, xs, d, true, yv);
-      gemv_range<BT, (RR > 0 ? 2 : 8)>(Bg, a.ldb, g0, nrows, xs, d, a.vec_ok != 0, yv);
+      gemv_regrows<BT, NV, RR>(R, cr, nreg, xs, scale, yv);
+      gemv_range<BT, 4>(Bs, a.ldsB, 0, cr, xs, d, true, scale, yv);
+      gemv_range<BT, (RR > 0 ? 2 : 8)>(Bg, a.ldb, g0, nrows, xs, d, a.vec_ok != 0, scale, yv);
       __syncthreads();
       it++;
       // ---- publish y (own rows) and the block partials ||y_R||^2, x_R . y_R
       ++epoch;
       uint64_t* xb = a.xex + (int64_t)(nx & 1) * xwords; nx++;
       uint64_t* pb = a.pex + (int64_t)(np & 1) * G * a.pw; np++;
-      if (wave == 0) {
+      for (int i = tid; i < nrows; i += 256) {
+        if constexpr (sizeof(BT) == 4) ll_store(xb + (r0 + i), epoch, __float_as_uint((float)yv[i]));
+        else ll_store_f64(xb + 2 * (int64_t)(r0 + i), epoch, yv[i]);
+      }
+      if (wave == 3) {
         double q = 0.0, dd = 0.0;
         for (int i = lane; i < nrows; i += 64) { q = fma(yv[i], yv[i], q); dd = fma(xv[i], yv[i], dd); }
         q = wave_sum(q);
         dd = wave_sum(dd);
         if (lane == 0) { ll_store_f64(pb + 4 * (int64_t)b, epoch, q); ll_store_f64(pb + 4 * (int64_t)b + 2, epoch, dd); }
-      }
-      for (int i = tid; i < nrows; i += 256) {
-        if constexpr (sizeof(BT) == 4) ll_store(xb + (r0 + i), epoch, __float_as_uint((float)yv[i]));
-        else ll_store_f64(xb + 2 * (int64_t)(r0 + i), epoch, yv[i]);
       }
       // ---- one wait for every block's y and partials
       double q, dd;
@@ -528,22 +538,8 @@ __device__ int solve_problem(const PowerArgs& a, int b, int G, unsigned char* sm
         __syncthreads();
         break;
       }
-      // x = y / ||y|| (each thread scales the entries it gathered: same index set)
-      {
-        const int count = d * (int)(sizeof(BT) / 4);
-        const int rot = (int)(((int64_t)b * 1031) % count);
-        if constexpr (sizeof(BT) == 4) {
-          for (int i = tid; i < count; i += 256) {
-            int ii = i + rot;
-            if (ii >= count) ii -= count;
-            xs[ii] = (BT)((double)xs[ii] * inv);
-          }
-        }
-      }
-      __syncthreads();
-      if constexpr (sizeof(BT) == 8) {
-        for (int c = tid; c < d; c += 256) xs[c] = xs[c] * inv;
-      }
+      // x_{t+1} = y / ||y||: xs keeps y, the next row sums are scaled by 1 / ||y||
+      scale = inv;
       for (int i = tid; i < nrows; i += 256) xv[i] = yv[i] * inv;
       __syncthreads();
     }
@@ -603,8 +599,8 @@ __device__ int solve_problem(const PowerArgs& a, int b, int G, unsigned char* sm
     uint64_t* vb = a.vex + (int64_t)(l & 1) * a.vstride;
     for (int i = tid; i < nrows; i += 256) ll_store_f64(vb + 2 * (int64_t)(r0 + i), epoch, vv[i]);
     if (!gather_f64_as<BT>(vb, epoch, d, xs, flag, a.spin_limit)) { err = ERR_SPIN; break; }
-    gemv_range<BT>(Bs, a.ldsB, 0, cr, xs, d, true, wv);
-    gemv_range<BT, (RR > 0 ? 2 : 8)>(Bg, a.ldb, cr, nrows, xs, d, a.vec_ok != 0, wv);
+    gemv_range<BT, 4>(Bs, a.ldsB, 0, cr, xs, d, true, 1.0, wv);
+    gemv_range<BT, (RR > 0 ? 2 : 8)>(Bg, a.ldb, cr, nrows, xs, d, a.vec_ok != 0, 1.0, wv);
     __syncthreads();
     if (tid == 0) {
       double al = 0.0;
