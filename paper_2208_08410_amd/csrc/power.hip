@@ -113,7 +113,7 @@ __device__ __forceinline__ void gemv_rows(const BT* rows, int64_t stride, int fi
 // all.  The wave index is made explicitly uniform so the row-count dispatch is
 // a scalar branch.
 template <typename BT, int UNR = 2>
-__device__ void gemv_range(const BT* rows, int64_t stride, int begin, int end, const BT* xs, int d, bool vec_ok,
+__device__ __forceinline__ void gemv_range(const BT* rows, int64_t stride, int begin, int end, const BT* xs, int d, bool vec_ok,
                            double scale, double* yout) {
   constexpr int VN = VecOf<BT>::N;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -179,7 +179,7 @@ __device__ __forceinline__ void gemv_regrows(const RegRows<BT, NV, RR>& R, int c
 // Sum vals[0..P) over all G workgroups (published in the partial buffer under
 // epoch ex); out[0..P) receives the totals, identical in every workgroup.
 // Returns false (uniformly in the block) if a wait ran out of budget.
-__device__ bool allreduce_blocks(uint64_t* pbuf, int pw, int b, int G, uint32_t ex, const double* vals, int P,
+__device__ __forceinline__ bool allreduce_blocks(uint64_t* pbuf, int pw, int b, int G, uint32_t ex, const double* vals, int P,
                                  double* out, double* scratch, int* flag, int64_t spin_limit) {
   const int tid = threadIdx.x;
   for (int j = tid; j < P; j += 256) ll_store_f64(pbuf + (int64_t)b * pw + 2 * j, ex, vals[j]);
@@ -246,61 +246,15 @@ __device__ bool allreduce_blocks(uint64_t* pbuf, int pw, int b, int G, uint32_t 
   return res;
 }
 
-// Gather a published FP64 vector (2 words per element) into dst as BT.
-template <typename BT>
-__device__ bool gather_f64_as(const uint64_t* buf, uint32_t ex, int d, BT* dst, int* flag, int64_t spin_limit) {
-  if (threadIdx.x == 0) *flag = 1;
-  __syncthreads();
-  int64_t budget = spin_limit;
-  bool ok = true;
-  constexpr int W = 8;
-  for (int base = 0; base < d && ok; base += 256 * W) {
-    uint64_t lo[W], hi[W];
-#pragma unroll
-    for (int j = 0; j < W; j++) {
-      const int e = base + threadIdx.x + 256 * j;
-      if (e < d) { lo[j] = ll_load(buf + 2 * (int64_t)e); hi[j] = ll_load(buf + 2 * (int64_t)e + 1); }
-      else lo[j] = hi[j] = ((uint64_t)ex << 32);
-    }
-    while (true) {
-      bool all = true;
-#pragma unroll
-      for (int j = 0; j < W; j++) all = all && ((uint32_t)(lo[j] >> 32) == ex) && ((uint32_t)(hi[j] >> 32) == ex);
-      if (all) break;
-      if (--budget <= 0) { ok = false; break; }
-      __builtin_amdgcn_s_sleep(1);
-#pragma unroll
-      for (int j = 0; j < W; j++) {
-        const int e = base + threadIdx.x + 256 * j;
-        if (e < d) {
-          if ((uint32_t)(lo[j] >> 32) != ex) lo[j] = ll_load(buf + 2 * (int64_t)e);
-          if ((uint32_t)(hi[j] >> 32) != ex) hi[j] = ll_load(buf + 2 * (int64_t)e + 1);
-        }
-      }
-    }
-    if (ok) {
-#pragma unroll
-      for (int j = 0; j < W; j++) {
-        const int e = base + threadIdx.x + 256 * j;
-        if (e < d) dst[e] = (BT)ll_join_f64(lo[j], hi[j]);
-      }
-    }
-  }
-  if (!ok) *flag = 0;
-  __syncthreads();
-  const bool res = *flag != 0;
-  __syncthreads();
-  return res;
-}
-
 // Iteration exchange: wait until every y word of this epoch (rotated start per
 // block to spread the requests over memory channels) and every block's two
 // partials are published; y lands in xs (raw), partials are summed with a
-// fixed-shape tree.  Returns false (block-uniform) on a timed-out wait.
+// fixed-shape tree.  With G = 0 only the vector is gathered (q = dd = 0).
+// Returns false (block-uniform) on a timed-out wait.
 // W words per thread per round: 16 puts up to 4096 words in flight at once
 // (one round for a 4096-entry FP32 iterate), 8 keeps registers for smaller d.
 template <typename BT, int W>
-__device__ bool gather_iteration(const uint64_t* xb, const uint64_t* pb, uint32_t ex, int d, int b, int G, BT* xs,
+__device__ __forceinline__ bool gather_iteration(const uint64_t* xb, const uint64_t* pb, uint32_t ex, int d, int b, int G, BT* xs,
                                  double* red, int* flag, int64_t spin_limit, double& q, double& dd) {
   constexpr int WPE = sizeof(BT) / 4;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -368,16 +322,69 @@ __device__ bool gather_iteration(const uint64_t* xb, const uint64_t* pb, uint32_
   return res;
 }
 
-// B[li][c] -= coef[li] * z[c] for every own row li (LDS rows [0, cr), the
-// rest in B) and column c < d; z is a vector in LDS.
+// row[c] -= coef[li] * z[c] for rows li in [begin, end) of one storage (LDS or
+// HBM) and columns c < d; z is a vector in LDS.  FP64 arithmetic, rounded once
+// to B's type; the column loop is unrolled so that several row chunks are in
+// flight.
 template <typename BT>
-__device__ void deflate_rows(const PowerArgs& a, BT* Bs, BT* Bg, int cr, int nrows, const BT* z, const double* coef) {
+__device__ __forceinline__ void deflate_rows(BT* rows, int64_t stride, int begin, int end, bool vec_ok, int d, const BT* z,
+                             const double* coef) {
+  constexpr int VN = VecOf<BT>::N;
+  using VT = typename std::conditional<sizeof(BT) == 4, float4, double2>::type;
   const int tid = threadIdx.x;
-  const int d = a.d;
-  for (int li = 0; li < nrows; li++) {
-    BT* row = li < cr ? Bs + (int64_t)li * a.ldsB : Bg + (int64_t)li * a.ldb;
+  const int dv = vec_ok ? (d / VN) * VN : 0;
+  for (int li = begin; li < end; li++) {
+    BT* row = rows + (int64_t)li * stride;
     const double ci = coef[li];
-    for (int c = tid; c < d; c += 256) row[c] = (BT)fma(-ci, (double)z[c], (double)row[c]);
+#pragma unroll 4
+    for (int c = tid * VN; c < dv; c += 256 * VN) {
+      VT r = *(const VT*)(row + c);
+      const VT zz = *(const VT*)(z + c);
+      if constexpr (VN == 4) {
+        r.x = (BT)fma(-ci, (double)zz.x, (double)r.x);
+        r.y = (BT)fma(-ci, (double)zz.y, (double)r.y);
+        r.z = (BT)fma(-ci, (double)zz.z, (double)r.z);
+        r.w = (BT)fma(-ci, (double)zz.w, (double)r.w);
+      } else {
+        r.x = (BT)fma(-ci, (double)zz.x, (double)r.x);
+        r.y = (BT)fma(-ci, (double)zz.y, (double)r.y);
+      }
+      *(VT*)(row + c) = r;
+    }
+    for (int c = dv + tid; c < d; c += 256) row[c] = (BT)fma(-ci, (double)z[c], (double)row[c]);
+  }
+}
+
+// The same update on the register rows (columns c >= d keep their zeros).
+template <typename BT, int NV, int RR>
+__device__ __forceinline__ void deflate_regrows(RegRows<BT, NV, RR>& R, int cr, int nreg, int d, const BT* z,
+                                                const double* coef) {
+  if constexpr (RR > 0 && NV > 0) {
+    if (nreg <= 0) return;
+    constexpr int VN = VecOf<BT>::N;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < RR; q++) {
+      const int li = wave + 4 * q;
+      const double ci = li < nreg ? coef[cr + li] : 0.0;
+#pragma unroll
+      for (int s = 0; s < NV; s++) {
+        BT zv[VN];
+        if constexpr (VN == 4) {
+          const float4 f = *(const float4*)(z + VN * lane + 64 * VN * s);
+          zv[0] = f.x; zv[1] = f.y; zv[2] = f.z; zv[3] = f.w;
+        } else {
+          const double2 f = *(const double2*)(z + VN * lane + 64 * VN * s);
+          zv[0] = f.x; zv[1] = f.y;
+        }
+#pragma unroll
+        for (int e = 0; e < VN; e++) {
+          const int c = VN * lane + 64 * VN * s + e;
+          const BT nv = (BT)fma(-ci, (double)zv[e], (double)R.v[q][s][e]);
+          R.v[q][s][e] = c < d ? nv : R.v[q][s][e];
+        }
+      }
+    }
   }
 }
 
@@ -402,32 +409,11 @@ __device__ __forceinline__ void load_regrows(RegRows<BT, NV, RR>& R, const BT* B
   }
 }
 
-template <typename BT, int NV, int RR>
-__device__ __forceinline__ void store_regrows(const RegRows<BT, NV, RR>& R, BT* Bg, int64_t ldb, int cr, int nreg,
-                                              int d) {
-  if constexpr (RR > 0 && NV > 0) {
-    constexpr int VN = VecOf<BT>::N;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int q = 0; q < RR; q++) {
-      const bool live = wave + 4 * q < nreg;
-      BT* row = Bg + (int64_t)(cr + wave + 4 * q) * ldb;
-#pragma unroll
-      for (int s = 0; s < NV; s++)
-#pragma unroll
-        for (int e = 0; e < VN; e++) {
-          const int c = VN * lane + 64 * VN * s + e;
-          if (live && c < d) row[c] = R.v[q][s][e];
-        }
-    }
-  }
-}
-
 // One problem solved by a team of G workgroups (this one is member b).  The
 // exchange counters persist across problems solved by the same team.  Returns
 // the error code this workgroup met (ERR_NONE on success).
 template <typename BT, int NV, int RR>
-__device__ int solve_problem(const PowerArgs& a, int b, int G, unsigned char* smem, uint32_t& epoch, uint32_t& nx,
+__device__ __forceinline__ int solve_problem(const PowerArgs& a, int b, int G, unsigned char* smem, uint32_t& epoch, uint32_t& nx,
                               uint32_t& np) {
   constexpr int VN = VecOf<BT>::N;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -468,16 +454,21 @@ __device__ int solve_problem(const PowerArgs& a, int b, int G, unsigned char* sm
   int err = ERR_NONE;
   int kdone = a.k;
   bool all_conv = true, rankdef = false;
+  // register rows stay resident for the whole launch and are deflated in place
+  RegRows<BT, NV, RR> R;
+  load_regrows<BT, NV, RR>(R, Bg, a.ldb, cr, nreg, d);
 
   for (int l = 0; l < a.k; l++) {
     // ---- start vector x = v0_l / ||v0_l|| (every block computes the same norm)
     const double* v0 = a.v0 + (int64_t)l * d;
     double ss = 0.0;
+#pragma unroll 8
     for (int c = tid; c < d; c += 256) ss = fma(v0[c], v0[c], ss);
     ss = block_sum(ss, redw, tid, 256);
     if (!isfinite(ss)) { err = ERR_NONFINITE; break; }
     if (!(ss > 0.0)) { err = ERR_BADSTART; break; }
     const double inv0 = 1.0 / sqrt(ss);
+#pragma unroll 8
     for (int c = tid; c < dpad; c += 256) xs[c] = c < d ? (BT)(v0[c] * inv0) : (BT)0;
     for (int i = tid; i < nrows; i += 256) xv[i] = v0[r0 + i] * inv0;
     __syncthreads();
@@ -490,10 +481,6 @@ __device__ int solve_problem(const PowerArgs& a, int b, int G, unsigned char* sm
     // normalisation 1 / ||y_t|| is applied to the next product's row sums
     // instead of to the iterate (the same value without a pass over xs)
     double scale = 1.0;
-    // register rows live only for this triplet's iterations: loaded from B here,
-    // written back before the deflation (which updates them in B)
-    RegRows<BT, NV, RR> R;
-    load_regrows<BT, NV, RR>(R, Bg, a.ldb, cr, nreg, d);
     while (true) {
       // ---- y = B x on the block's rows
       gemv_regrows<BT, NV, RR>(R, cr, nreg, xs, scale, yv);
@@ -545,18 +532,33 @@ __device__ int solve_problem(const PowerArgs& a, int b, int G, unsigned char* sm
     }
     if (err != ERR_NONE || rankdef) break;
     if (!conv) all_conv = false;
-    if (l + 1 < a.k) store_regrows<BT, NV, RR>(R, Bg, a.ldb, cr, nreg, d);
 
     // ---- FP64 re-orthogonalisation of v against X[:, 0..l)
     const int P = l + 1;  // c_j = X[:, j] . v (j < l) and ||v||^2 (j = l)
-    for (int j = wave; j < P; j += 4) {
-      double s = 0.0;
-      for (int i = lane; i < nrows; i += 64) {
-        const double xi = (j < l) ? a.X[(int64_t)j * a.ldx + r0 + i] : vv[i];
-        s = fma(xi, vv[i], s);
+    {
+      // wave w takes j = w, w + 4, ...; JB of them per pass so that their X
+      // loads are in flight together (j >= l reads a valid column and is
+      // replaced by v)
+      constexpr int JB = 8;
+      const int jmax = l > 0 ? l - 1 : 0;
+      for (int j0 = wave; j0 < P; j0 += 4 * JB) {
+        double sj[JB];
+#pragma unroll
+        for (int u = 0; u < JB; u++) sj[u] = 0.0;
+        for (int i = lane; i < nrows; i += 64) {
+          const double vi = vv[i];
+          double xj[JB];
+#pragma unroll
+          for (int u = 0; u < JB; u++) xj[u] = a.X[(int64_t)min(j0 + 4 * u, jmax) * a.ldx + r0 + i];
+#pragma unroll
+          for (int u = 0; u < JB; u++) sj[u] = fma(j0 + 4 * u < l ? xj[u] : vi, vi, sj[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < JB; u++) {
+          const double t = wave_sum(sj[u]);
+          if (lane == 0 && j0 + 4 * u < P) kvals[j0 + 4 * u] = t;
+        }
       }
-      s = wave_sum(s);
-      if (lane == 0) kvals[j] = s;
     }
     __syncthreads();
     ++epoch;
@@ -564,10 +566,30 @@ __device__ int solve_problem(const PowerArgs& a, int b, int G, unsigned char* sm
       uint64_t* pb = a.pex + (int64_t)(np & 1) * G * a.pw; np++;
       if (!allreduce_blocks(pb, a.pw, b, G, epoch, kvals, P, ktot, scratch, flag, a.spin_limit)) { err = ERR_SPIN; break; }
     }
-    for (int i = tid; i < nrows; i += 256) {
-      double v = vv[i];
-      for (int j = 0; j < l; j++) v = fma(-a.X[(int64_t)j * a.ldx + r0 + i], ktot[j], v);
-      vv[i] = v;
+    if (nrows <= 128) {
+      // v_i -= sum_j X[i][j] c_j with the j range split over parts = 256 / nrows
+      // threads per row (their loads in flight together), parts added in order
+      const int parts = nrows > 0 ? 256 / nrows : 1;
+      const int i = nrows > 0 ? tid % nrows : 0, part = nrows > 0 ? tid / nrows : 0;
+      double acc = 0.0;
+      if (part < parts) {
+#pragma unroll 4
+        for (int j = part; j < l; j += parts) acc = fma(a.X[(int64_t)j * a.ldx + r0 + i], ktot[j], acc);
+        scratch[part * nrows + i] = acc;
+      }
+      __syncthreads();
+      if (tid < nrows) {
+        double t = 0.0;
+        for (int p2 = 0; p2 < parts; p2++) t += scratch[p2 * nrows + tid];
+        vv[tid] -= t;
+      }
+    } else {
+      for (int i = tid; i < nrows; i += 256) {
+        double v = vv[i];
+#pragma unroll 8
+        for (int j = 0; j < l; j++) v = fma(-a.X[(int64_t)j * a.ldx + r0 + i], ktot[j], v);
+        vv[i] = v;
+      }
     }
     __syncthreads();
     {
@@ -595,12 +617,21 @@ __device__ int solve_problem(const PowerArgs& a, int b, int G, unsigned char* sm
     if (l + 1 >= a.k) break;
 
     // ---- deflation: w = B v, alpha = v.w, B <- B - v w^T - w v^T + alpha v v^T
+    // v and w travel as B's type (the GEMV and the update read them as such)
+    constexpr int WG = (NV <= 16) ? 16 : 8;  // gather width (registers permitting)
     ++epoch;
     uint64_t* vb = a.vex + (int64_t)(l & 1) * a.vstride;
-    for (int i = tid; i < nrows; i += 256) ll_store_f64(vb + 2 * (int64_t)(r0 + i), epoch, vv[i]);
-    if (!gather_f64_as<BT>(vb, epoch, d, xs, flag, a.spin_limit)) { err = ERR_SPIN; break; }
+    for (int i = tid; i < nrows; i += 256) {
+      if constexpr (sizeof(BT) == 4) ll_store(vb + (r0 + i), epoch, __float_as_uint((float)vv[i]));
+      else ll_store_f64(vb + 2 * (int64_t)(r0 + i), epoch, vv[i]);
+    }
+    {
+      double q0, d0;
+      if (!gather_iteration<BT, WG>(vb, vb, epoch, d, b, 0, xs, redw, flag, a.spin_limit, q0, d0)) { err = ERR_SPIN; break; }
+    }
+    gemv_regrows<BT, NV, RR>(R, cr, nreg, xs, 1.0, wv);
     gemv_range<BT, 4>(Bs, a.ldsB, 0, cr, xs, d, true, 1.0, wv);
-    gemv_range<BT, (RR > 0 ? 2 : 8)>(Bg, a.ldb, cr, nrows, xs, d, a.vec_ok != 0, 1.0, wv);
+    gemv_range<BT, (RR > 0 ? 2 : 8)>(Bg, a.ldb, g0, nrows, xs, d, a.vec_ok != 0, 1.0, wv);
     __syncthreads();
     if (tid == 0) {
       double al = 0.0;
@@ -611,7 +642,10 @@ __device__ int solve_problem(const PowerArgs& a, int b, int G, unsigned char* sm
     ++epoch;
     const uint32_t wep = epoch;
     uint64_t* wb = a.wex + (int64_t)(l & 1) * a.vstride;
-    for (int i = tid; i < nrows; i += 256) ll_store_f64(wb + 2 * (int64_t)(r0 + i), wep, wv[i]);
+    for (int i = tid; i < nrows; i += 256) {
+      if constexpr (sizeof(BT) == 4) ll_store(wb + (r0 + i), wep, __float_as_uint((float)wv[i]));
+      else ll_store_f64(wb + 2 * (int64_t)(r0 + i), wep, wv[i]);
+    }
     {
       uint64_t* pb = a.pex + (int64_t)(np & 1) * G * a.pw; np++;
       if (!allreduce_blocks(pb, a.pw, b, G, epoch, sv + 3, 1, st + 5, scratch, flag, a.spin_limit)) { err = ERR_SPIN; break; }
@@ -623,10 +657,17 @@ __device__ int solve_problem(const PowerArgs& a, int b, int G, unsigned char* sm
     // and rounded to B's type.
     for (int i = tid; i < nrows; i += 256) xv[i] = wv[i] - alpha * vv[i];  // beta (own rows)
     __syncthreads();
-    deflate_rows<BT>(a, Bs, Bg, cr, nrows, xs, xv);
+    deflate_rows<BT>(Bs, a.ldsB, 0, cr, true, d, xs, xv);
+    deflate_regrows<BT, NV, RR>(R, cr, nreg, d, xs, xv);
+    deflate_rows<BT>(Bg, a.ldb, g0, nrows, a.vec_ok != 0, d, xs, xv);
     __syncthreads();
-    if (!gather_f64_as<BT>(wb, wep, d, xs, flag, a.spin_limit)) { err = ERR_SPIN; break; }
-    deflate_rows<BT>(a, Bs, Bg, cr, nrows, xs, vv);
+    {
+      double q0, d0;
+      if (!gather_iteration<BT, WG>(wb, wb, wep, d, b, 0, xs, redw, flag, a.spin_limit, q0, d0)) { err = ERR_SPIN; break; }
+    }
+    deflate_rows<BT>(Bs, a.ldsB, 0, cr, true, d, xs, vv);
+    deflate_regrows<BT, NV, RR>(R, cr, nreg, d, xs, vv);
+    deflate_rows<BT>(Bg, a.ldb, g0, nrows, a.vec_ok != 0, d, xs, vv);
     __syncthreads();
   }
 
