@@ -42,6 +42,12 @@ __device__ __forceinline__ void ll_store_f64(uint64_t* p, uint32_t epoch, double
   ll_store(p + 1, epoch, (uint32_t)(b >> 32));
 }
 
+// low (half = 0) or high (half = 1) 32 bits of a double, as published by ll_store_f64
+__device__ __forceinline__ uint32_t f64_half(double v, int half) {
+  const uint64_t b = __double_as_longlong(v);
+  return half ? (uint32_t)(b >> 32) : (uint32_t)b;
+}
+
 __device__ __forceinline__ double ll_join_f64(uint64_t lo, uint64_t hi) {
   return __longlong_as_double((long long)(((hi & 0xffffffffull) << 32) | (lo & 0xffffffffull)));
 }

@@ -182,7 +182,7 @@ __device__ __forceinline__ void gemv_regrows(const RegRows<BT, NV, RR>& R, int c
 __device__ __forceinline__ bool allreduce_blocks(uint64_t* pbuf, int pw, int b, int G, uint32_t ex, const double* vals, int P,
                                  double* out, double* scratch, int* flag, int64_t spin_limit) {
   const int tid = threadIdx.x;
-  for (int j = tid; j < P; j += 256) ll_store_f64(pbuf + (int64_t)b * pw + 2 * j, ex, vals[j]);
+  for (int w = tid; w < 2 * P; w += 256) ll_store(pbuf + (int64_t)b * pw + w, ex, f64_half(vals[w >> 1], w & 1));
   if (tid == 0) *flag = 1;
   __syncthreads();
   for (int jb = 0; jb < P; jb += 256) {
@@ -244,6 +244,18 @@ __device__ __forceinline__ bool allreduce_blocks(uint64_t* pbuf, int pw, int b, 
   const bool res = *flag != 0;
   __syncthreads();
   return res;
+}
+
+// Publish own rows r0 + i (i < nrows) of a vector in B's type: one word per
+// FP32 element, two (low, high half) per FP64 element, each thread storing
+// one word so that a wave's words leave in one store instruction.
+template <typename BT>
+__device__ __forceinline__ void publish_rows(uint64_t* buf, uint32_t ep, int r0, int nrows, const double* v) {
+  if constexpr (sizeof(BT) == 4) {
+    for (int i = threadIdx.x; i < nrows; i += 256) ll_store(buf + r0 + i, ep, __float_as_uint((float)v[i]));
+  } else {
+    for (int w = threadIdx.x; w < 2 * nrows; w += 256) ll_store(buf + 2 * (int64_t)r0 + w, ep, f64_half(v[w >> 1], w & 1));
+  }
 }
 
 // Iteration exchange: wait until every y word of this epoch (rotated start per
@@ -492,16 +504,15 @@ __device__ __forceinline__ int solve_problem(const PowerArgs& a, int b, int G, u
       ++epoch;
       uint64_t* xb = a.xex + (int64_t)(nx & 1) * xwords; nx++;
       uint64_t* pb = a.pex + (int64_t)(np & 1) * G * a.pw; np++;
-      for (int i = tid; i < nrows; i += 256) {
-        if constexpr (sizeof(BT) == 4) ll_store(xb + (r0 + i), epoch, __float_as_uint((float)yv[i]));
-        else ll_store_f64(xb + 2 * (int64_t)(r0 + i), epoch, yv[i]);
-      }
+      publish_rows<BT>(xb, epoch, r0, nrows, yv);
       if (wave == 3) {
         double q = 0.0, dd = 0.0;
         for (int i = lane; i < nrows; i += 64) { q = fma(yv[i], yv[i], q); dd = fma(xv[i], yv[i], dd); }
         q = wave_sum(q);
         dd = wave_sum(dd);
-        if (lane == 0) { ll_store_f64(pb + 4 * (int64_t)b, epoch, q); ll_store_f64(pb + 4 * (int64_t)b + 2, epoch, dd); }
+        // the four words (q lo/hi, dd lo/hi) go out in one store instruction:
+        // a wave's device-scope stores become visible one after another
+        if (lane < 4) ll_store(pb + 4 * (int64_t)b + lane, epoch, f64_half(lane < 2 ? q : dd, lane & 1));
       }
       // ---- one wait for every block's y and partials
       double q, dd;
@@ -621,10 +632,7 @@ __device__ __forceinline__ int solve_problem(const PowerArgs& a, int b, int G, u
     constexpr int WG = (NV <= 16) ? 16 : 8;  // gather width (registers permitting)
     ++epoch;
     uint64_t* vb = a.vex + (int64_t)(l & 1) * a.vstride;
-    for (int i = tid; i < nrows; i += 256) {
-      if constexpr (sizeof(BT) == 4) ll_store(vb + (r0 + i), epoch, __float_as_uint((float)vv[i]));
-      else ll_store_f64(vb + 2 * (int64_t)(r0 + i), epoch, vv[i]);
-    }
+    publish_rows<BT>(vb, epoch, r0, nrows, vv);
     {
       double q0, d0;
       if (!gather_iteration<BT, WG>(vb, vb, epoch, d, b, 0, xs, redw, flag, a.spin_limit, q0, d0)) { err = ERR_SPIN; break; }
@@ -642,10 +650,7 @@ __device__ __forceinline__ int solve_problem(const PowerArgs& a, int b, int G, u
     ++epoch;
     const uint32_t wep = epoch;
     uint64_t* wb = a.wex + (int64_t)(l & 1) * a.vstride;
-    for (int i = tid; i < nrows; i += 256) {
-      if constexpr (sizeof(BT) == 4) ll_store(wb + (r0 + i), wep, __float_as_uint((float)wv[i]));
-      else ll_store_f64(wb + 2 * (int64_t)(r0 + i), wep, wv[i]);
-    }
+    publish_rows<BT>(wb, wep, r0, nrows, wv);
     {
       uint64_t* pb = a.pex + (int64_t)(np & 1) * G * a.pw; np++;
       if (!allreduce_blocks(pb, a.pw, b, G, epoch, sv + 3, 1, st + 5, scratch, flag, a.spin_limit)) { err = ERR_SPIN; break; }
