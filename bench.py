@@ -76,29 +76,44 @@ def parse():
     return ap.parse_args()
 
 
+TRAFFIC_SOURCES = {
+    # key -> (file under csrc/, marker that starts its host-side part, or None for the whole file)
+    "power.hip-device": ("power.hip", "// Host side"),
+    "syrk.hip-device": ("syrk.hip", "// Host launchers"),
+    "common.h": ("common.h", None),
+}
+
+
+def source_hash(key: str) -> str:
+    import hashlib
+    name, marker = TRAFFIC_SOURCES[key]
+    text = open(os.path.join(ROOT, "paper_2208_08410_amd", "csrc", name)).read()
+    if marker:
+        text = text[:text.index(marker)]
+    return hashlib.sha256(text.encode()).hexdigest()[:16]
+
+
 def measured_traffic(kernel: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary (FETCH_SIZE, WRITE_SIZE scaled by a reference copy), or None when
-    the kernel's device source has changed since the counters were taken."""
-    import hashlib
+    the device source the kernel is built from has changed since the counters
+    were taken."""
     path = os.path.join(ROOT, "profiles", "traffic_power_gram_finish_dense_200000x4096_k64.txt")
-    csrc = os.path.join(ROOT, "paper_2208_08410_amd", "csrc")
     try:
         lines = open(path).read().splitlines()
-        power = open(os.path.join(csrc, "power.hip")).read()
-        common = open(os.path.join(csrc, "common.h")).read()
     except OSError:
         return None
-    now = {"power.hip-device": hashlib.sha256(power[:power.index("// Host side")].encode()).hexdigest()[:16],
-           "common.h": hashlib.sha256(common.encode()).hexdigest()[:16]}
+    recorded = {}
     for l in lines:
         if l.startswith("sha256-16 "):
-            _, name, h = l.split()
-            if now.get(name) != h:
-                return None
+            _, key, h = l.split()
+            recorded[key] = h
     for l in lines:
         if l.startswith("kernel " + kernel + " "):
             f = dict(kv.split("=") for kv in l.split()[2:])
+            for key in f.get("sources", "").split(","):
+                if key not in TRAFFIC_SOURCES or recorded.get(key) != source_hash(key):
+                    return None
             return float(f["fetch_kib"]) * 1024 * float(f["fetch_scale"]) + \
                 float(f["write_kib"]) * 1024 * float(f["write_scale"])
     return None
@@ -573,22 +588,28 @@ def main():
     pbytes, punits = power_bytes_per_launch(info["iters"], a.k, a.n)
     phases = {"gram": t_gram, "power": t_eig, "finish": t_fin}
     dominant = max(phases, key=phases.get)
-    nt = (a.n + 127) // 128
-    gram_flops_hw = 3 * 2.0 * a.m * (nt * (nt + 1) // 2) * 128 * 128 if a.gram == "bf16x3" else \
-        2.0 * a.m * (nt * (nt + 1) // 2) * 128 * 128
+    # the library's default tiles: 256 x 256 for BF16X3 Grams of dimension >= 1024, else 128 x 128
+    bm = 256 if (a.gram == "bf16x3" and a.n >= 1024) else 128
+    nt = (a.n + bm - 1) // bm
+    gram_flops_hw = (3 if a.gram == "bf16x3" else 1) * 2.0 * a.m * (nt * (nt + 1) // 2) * bm * bm
+    gram_kernel = ("syrk_bf16x3_big_kernel<0> + syrk_reduce_kernel<float,256>" if bm == 256 else
+                   "syrk_partial_kernel<%s,0> + syrk_reduce_kernel<float,128>" % a.gram)
+    c2_shape = a.n == 4096 and a.m == 200000 and a.k == 64
     gram_flops_alg = 1.0 * a.m * a.n * (a.n + 1)
     gram_peak = BF16_PEAK_TFLOPS if a.gram == "bf16x3" else FP32_PEAK_TFLOPS
     roof_gram = {
-        "kernel": "syrk_partial_kernel<%s> + syrk_reduce_kernel" % a.gram,
+        "kernel": gram_kernel,
         "bound": "mfma",
         "achieved": gram_flops_hw / (t_gram * 1e-3) / 1e12,
         "peak": gram_peak,
         "unit": "TFLOP/s",
         "frac": gram_flops_hw / (t_gram * 1e-3) / 1e12 / gram_peak,
-        "traffic": None,
+        "traffic": measured_traffic("syrk_bf16x3_big_kernel<0>+syrk_reduce_kernel<float,256>")
+        if (c2_shape and bm == 256) else None,
+        "traffic_note": "HBM bytes per launch pair from profiles/traffic_*.txt; A alone is m*n*4 bytes",
         "effective_fp32_equiv_tflops": gram_flops_alg / (t_gram * 1e-3) / 1e12,
     }
-    traffic = measured_traffic("power_kernel<float,16,2>") if a.n == 4096 and a.m == 200000 and a.k == 64 else None
+    traffic = measured_traffic("power_kernel<float,16,2>") if c2_shape else None
     roof_power = {
         "kernel": "power_kernel<float,16,2>",
         "bound": "hbm",

@@ -124,12 +124,13 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
 }
 
 // Sum over the 64 lanes in a fixed order (pairs, quads, 8, 16, then rows);
-// every lane returns the total.
+// every lane returns the total.  The first four patterns give every lane a
+// source inside its row, so they take bound_ctrl (no "old" operand to set up).
 __device__ __forceinline__ double wave_sum(double v) {
-  v += dpp_f64<0xB1, 0xF, false>(v);   // lane ^ 1
-  v += dpp_f64<0x4E, 0xF, false>(v);   // lane ^ 2
-  v += dpp_f64<0x141, 0xF, false>(v);  // mirror within 8: other quad
-  v += dpp_f64<0x140, 0xF, false>(v);  // mirror within 16: other half row
+  v += dpp_f64<0xB1, 0xF, true>(v);   // lane ^ 1
+  v += dpp_f64<0x4E, 0xF, true>(v);   // lane ^ 2
+  v += dpp_f64<0x141, 0xF, true>(v);  // mirror within 8: other quad
+  v += dpp_f64<0x140, 0xF, true>(v);  // mirror within 16: other half row
   v += dpp_f64<0x142, 0xA, false>(v);  // row 1 += row 0, row 3 += row 2
   v += dpp_f64<0x143, 0xC, false>(v);  // rows 2, 3 += lane 31 (rows 0 + 1)
   return readlane_f64(v, 63);
