@@ -75,7 +75,7 @@ def power_candidates(d: int, num_cu: int):
 
 
 def batch_candidates():
-    return [(tk, kc) for tk in (32, 64, 128, 256, 512) for kc in (1024, 2048, 4096)]
+    return [(tk, kc) for tk in (64, 128, 256, 512, 1024) for kc in (1024, 2048, 4096)]
 
 
 class Tuner:

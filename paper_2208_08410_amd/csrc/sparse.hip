@@ -158,12 +158,30 @@ __global__ __launch_bounds__(PB) void proj_partials_kernel(const double* V, int6
   }
 }
 
-// out[j] = sum_b partial[b][j] in block order (one block, threads over j)
-__global__ void reduce_partials_kernel(const double* partial, int64_t nb, int P, double* out) {
-  for (int j = threadIdx.x; j < P; j += blockDim.x) {
+// out[j] = sum_b partial[b][j] (one block of 256 threads).  Up to 256 outputs
+// per pass; each output's sum is split over 256 / outputs threads that add
+// strided partials (loads in flight together), and the thread sums are added
+// in thread order: a fixed association, independent of timing.
+__global__ __launch_bounds__(256) void reduce_partials_kernel(const double* partial, int64_t nb, int P, double* out) {
+  __shared__ double red[256];
+  const int tid = threadIdx.x;
+  for (int j0 = 0; j0 < P; j0 += 256) {
+    const int pc = P - j0 < 256 ? P - j0 : 256;
+    const int per = 256 / pc;
+    const int j = tid % pc, part = tid / pc;
     double s = 0.0;
-    for (int64_t b = 0; b < nb; b++) s += partial[b * P + j];
-    out[j] = s;
+    if (part < per) {
+#pragma unroll 8
+      for (int64_t b = part; b < nb; b += per) s += partial[b * P + j0 + j];
+    }
+    red[tid] = s;
+    __syncthreads();
+    if (tid < pc) {
+      double t = 0.0;
+      for (int q = 0; q < per; q++) t += red[q * pc + tid];
+      out[j0 + tid] = t;
+    }
+    __syncthreads();
   }
 }
 
@@ -285,7 +303,7 @@ int proj_apply_launch(const double* V, int64_t ldv, int l, const double* coef, d
                       double* out, hipStream_t s) {
   const int64_t nb = proj_blocks(d);
   hipLaunchKernelGGL(proj_apply_kernel, dim3((unsigned)nb), dim3(PB), 0, s, V, ldv, l, coef, w, d, partial);
-  hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(64), 0, s, partial, nb, 1, out);
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(256), 0, s, partial, nb, 1, out);
   TSVD_HIP_TRY(hipGetLastError());
   return 0;
 }
@@ -293,7 +311,7 @@ int proj_apply_launch(const double* V, int64_t ldv, int l, const double* coef, d
 int sumsq_launch(const double* v, int64_t d, double* partial, double* out, hipStream_t s) {
   const int64_t nb = proj_blocks(d);
   hipLaunchKernelGGL(sumsq_partial_kernel, dim3((unsigned)nb), dim3(PB), 0, s, v, d, partial);
-  hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(64), 0, s, partial, nb, 1, out);
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(256), 0, s, partial, nb, 1, out);
   TSVD_HIP_TRY(hipGetLastError());
   return 0;
 }
