@@ -53,7 +53,7 @@ def parse():
     ap.add_argument("--compare-fp32", type=int, default=1, help="also time the plain FP32 Gram mode")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--seed", type=int, default=2)
-    ap.add_argument("--workload", default="dense", choices=["dense", "serve", "stream", "sparse"])
+    ap.add_argument("--workload", default="dense", choices=["dense", "serve", "stream", "sparse", "batch"])
     ap.add_argument("--stream-m", type=int, default=2_000_000, help="stream: rows of the pinned-host A")
     ap.add_argument("--stream-n", type=int, default=8192)
     ap.add_argument("--stream-k", type=int, default=32)
@@ -73,6 +73,9 @@ def parse():
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serve: server device budget")
     ap.add_argument("--team-kib", type=int, default=0, help="serve: batched power team size rule (0 = library)")
     ap.add_argument("--max-batch", type=int, default=0, help="serve: requests per batch launch at most (0 = all)")
+    ap.add_argument("--batch-size", type=int, default=64, help="batch: problems per tsvd_dense_batched call")
+    ap.add_argument("--pool-gen", default="gpu", choices=["gpu", "cpu"],
+                    help="serve/batch: build the matrices on the GPU or on the host (then copy)")
     return ap.parse_args()
 
 
@@ -224,6 +227,102 @@ def _batch_phases(results):
             "finish": sum(t[2] for t in seen) / n, "total": sum(t[3] for t in seen) / n, "batches_seen": n}
 
 
+def request_pool(a, dev, loc):
+    """The serving mix's matrices: log-uniform shapes m in [1024, 65536], n in
+    [128, 4096], A = H_L [diag(0.95^i); 0] H_R, each with 64 start vectors."""
+    import torch
+
+    import synth
+
+    q = 0.95
+    g = synth.rng(a.seed, 77)
+    pool = []
+    progress(f"building a pool of {a.pool} matrices on the {a.pool_gen.upper()}")
+    gen_dev = dev if a.pool_gen == "gpu" else torch.device("cpu")
+    for j in range(a.pool):
+        m = int(round(math.exp(g.uniform(math.log(1024), math.log(65536)))))
+        n = int(round(math.exp(g.uniform(math.log(128), math.log(4096)))))
+        s = synth.spectrum_geometric(q, min(m, n))
+        A = synth.householder_known_torch(m, n, s, a.seed * 1000 + j, gen_dev)
+        if A.device != dev and loc != "host":
+            A = A.to(dev)
+        if loc == "host":
+            Ah = torch.empty((m, n), dtype=torch.float32, pin_memory=True)
+            Ah.copy_(A)
+            del A
+            A = Ah
+        d = min(m, n)
+        v0 = torch.from_numpy(synth.start_vectors(64, d, seed=a.seed * 1000 + j)).to(dev)
+        pool.append((A, v0, s))
+    torch.cuda.synchronize()
+    return pool
+
+
+def batch_main(a):
+    """Batched workload: a fixed batch of problems from the serving mix, solved
+    by one tsvd_dense_batched call per step (grouped Gram, power teams formed on
+    the fly, grouped finish), A resident in HBM."""
+    import numpy as np
+    import torch
+
+    import paper_2208_08410_amd as P
+    import synth
+
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    pool = request_pool(a, dev, "device")
+    gen_s = time.time() - t0
+    kch = synth.rng(a.seed, 88).choice([8, 16, 32, 64], size=a.batch_size)
+    pick = synth.rng(a.seed, 89).integers(0, a.pool, size=a.batch_size)
+    probs = [dict(A=pool[j][0], k=int(k), eps=a.eps, v0=pool[j][1][:int(k)], gram="bf16x3") for j, k in zip(pick, kch)]
+    ctx = P.Context(0)
+    if a.team_kib:
+        P.set_tuning(ctx, team_kib=a.team_kib)
+    progress(f"batch of {a.batch_size}: {a.warmup} warm-up and {a.steps} timed calls")
+    for _ in range(a.warmup):
+        P.tsvd_dense_batched(ctx, probs)
+    torch.cuda.synchronize()
+    t_s = time.perf_counter()
+    for _ in range(a.steps):
+        res = P.tsvd_dense_batched(ctx, probs)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t_s
+    statuses, errs = {}, []
+    for (U, S, V, info), j, k in zip(res, pick, kch):
+        statuses[info["status"]] = statuses.get(info["status"], 0) + 1
+        if info["status"] == "TSVD_OK":
+            s = pool[j][2]
+            errs.append(float(np.max(np.abs(S.cpu().numpy() - s[:k]) / s[:k])))
+    info0 = res[0][3]
+    ctx.close()
+    out = {
+        "metric": METRIC,
+        "value": a.batch_size * a.steps / dt,
+        "unit": "requests/s (batched, A in HBM)",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": dt * 1000 / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16x3/f32acc gram, f64 finish",
+        "data": "synthetic",
+        "config": {"workload": f"batch of {a.batch_size} problems from the serving mix (m log-uniform [1024, 65536], "
+                               f"n [128, 4096], k in {{8,16,32,64}}, s_i = 0.95^i), one tsvd_dense_batched call per "
+                               f"step, eps={a.eps}", "batch_size": a.batch_size, "pool": a.pool,
+                   "team_kib": a.team_kib},
+        "triplets_per_s": float(sum(int(k) for k in kch)) * a.steps / dt,
+        "phase_ms": {"gram": info0["t_gram_ms"], "power": info0["t_eig_ms"], "finish": info0["t_final_ms"]},
+        "statuses": statuses,
+        "sigma_rel_err_max": float(max(errs) if errs else float("nan")),
+        "meets_1e-6": bool(errs and max(errs) < 1e-6),
+        "gen_seconds": gen_s,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def serve_main(a):
     """Serving workload: Poisson arrivals into the library's request server."""
     import numpy as np
@@ -233,27 +332,9 @@ def serve_main(a):
     import synth
 
     dev = torch.device("cuda:0")
-    q = 0.95
     eps = a.eps
-    g = synth.rng(a.seed, 77)
-    # the pool: log-uniform shapes, A = H_L [diag(q^i); 0] H_R
     t0 = time.time()
-    pool = []
-    progress(f"building a pool of {a.pool} matrices")
-    for j in range(a.pool):
-        m = int(round(math.exp(g.uniform(math.log(1024), math.log(65536)))))
-        n = int(round(math.exp(g.uniform(math.log(128), math.log(4096)))))
-        s = synth.spectrum_geometric(q, min(m, n))
-        A = synth.householder_known_torch(m, n, s, a.seed * 1000 + j, dev)
-        if a.pool_loc == "host":
-            Ah = torch.empty((m, n), dtype=torch.float32, pin_memory=True)
-            Ah.copy_(A)
-            del A
-            A = Ah
-        d = min(m, n)
-        v0 = torch.from_numpy(synth.start_vectors(64, d, seed=a.seed * 1000 + j)).to(dev)
-        pool.append((A, v0, s))
-    torch.cuda.synchronize()
+    pool = request_pool(a, dev, a.pool_loc)
     gen_s = time.time() - t0
     total = a.warm + a.window
     count = int(a.rate * total * 1.5) + 16
@@ -534,6 +615,8 @@ def main():
         print("bench.py: this build runs on one GPU; multi-GPU (N > 1) is not implemented "
               "(the sharding design is described in DESIGN.md).", file=sys.stderr)
         return 2
+    if a.workload == "batch":
+        return batch_main(a)
     if a.workload == "serve":
         return serve_main(a)
     if a.workload == "stream":

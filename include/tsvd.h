@@ -217,8 +217,10 @@ typedef struct {
 /* Algorithm 1 for `count` independent problems of any mix of shapes, in three
  * grouped launches: the Gram of every problem (work units = problem x split-K
  * chunk x triangle tile, Algorithm 3's block products), one cooperative power
- * launch in which the CUs are split into teams that each run Algorithm 2 with
- * deflation on their list of problems, and the FP64 finishing product.  Each
+ * launch in which workgroups form a team per problem as they come free (the
+ * problems wait in a queue, longest first; a team runs Algorithm 2 with
+ * deflation on its problem, then its members return to the queue), and the
+ * FP64 finishing product.  Each
  * problem's result is what tsvd_dense computes for it, up to the rounding of a
  * different reduction order.  hbm_budget bounds the workspace of the whole
  * batch (0 = no limit).  infos (optional, count entries) receive per-problem

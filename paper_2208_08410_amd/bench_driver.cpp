@@ -8,6 +8,10 @@
 //   tsvd_bench copy BYTES [reps]
 //     a plain device-to-device copy kernel of BYTES (multiple of 16), the
 //     reference for scaling hardware traffic counters to bytes
+//   tsvd_bench batch COUNT [steps warmup seed]
+//     COUNT problems of the serving mix (m log-uniform in [1024, 65536], n in
+//     [128, 4096], k in {8, 16, 32, 64}, s_i = 0.95^i, eps = 5e-8) solved by
+//     one tsvd_dense_batched call per step, A resident in HBM
 //
 // A = H_L [diag(s); 0] H_R with s_i = 0.97^i and H_L, H_R products of two
 // random Householder reflectors (exactly orthogonal), so the singular values
@@ -65,21 +69,9 @@ static int run_copy(size_t bytes, int reps) {
   return 0;
 }
 
-int main(int argc, char** argv) {
-  if (argc > 1 && argv[1][0] == 'c')
-    return run_copy(argc > 2 ? strtoull(argv[2], nullptr, 10) : ((size_t)1 << 30), argc > 3 ? atoi(argv[3]) : 5);
-  const int64_t m = argc > 1 ? atoll(argv[1]) : 200000;
-  const int64_t n = argc > 2 ? atoll(argv[2]) : 4096;
-  const int k = argc > 3 ? atoi(argv[3]) : 64;
-  const double eps = argc > 4 ? atof(argv[4]) : 5e-8;
-  const int gram = argc > 5 ? atoi(argv[5]) : TSVD_GRAM_BF16X3;
-  const int steps = argc > 6 ? atoi(argv[6]) : 3;
-  const int warmup = argc > 7 ? atoi(argv[7]) : 1;
-  const uint64_t seed = argc > 8 ? strtoull(argv[8], nullptr, 10) : 7;
-  const size_t copy_bytes = argc > 9 ? strtoull(argv[9], nullptr, 10) : 0;
-  if (copy_bytes > 0 && run_copy(copy_bytes, 1) != 0) return 1;
-  if (m < n || k > n) { fprintf(stderr, "need m >= n >= k\n"); return 2; }
-
+// A = H_L [diag(s); 0] H_R (m >= n) into hA (row-major m x n FP32), with H_L,
+// H_R products of two random Householder reflectors.
+static void make_known(int64_t m, int64_t n, const std::vector<double>& s, uint64_t seed, float* hA) {
   // A = H_L [diag(s); 0] H_R, built row by row: row i of [diag(s); 0] H_R is
   // s_i * (row i of H_R) for i < n and 0 otherwise; H_L mixes rows through two
   // rank-1 corrections.
@@ -93,8 +85,6 @@ int main(int argc, char** argv) {
     for (auto& x : wl[r]) x *= a;
     for (auto& x : wr[r]) x *= b;
   }
-  std::vector<double> s(n);
-  for (int64_t i = 0; i < n; i++) s[i] = pow(0.97, (double)i);
   // D H_R rows: R_i = s_i e_i^T (I - 2 w1 w1^T)(I - 2 w2 w2^T)
   // M0 = [D H_R; 0]; A = (I - 2 u1 u1^T)(I - 2 u2 u2^T) M0
   // c_r = u_r^T M0 (n-vectors) are needed for the left reflectors.
@@ -120,8 +110,6 @@ int main(int argc, char** argv) {
   for (int64_t i = 0; i < n; i++)
     for (int64_t j = 0; j < n; j++) c2[j] += wl[1][i] * M0[(size_t)i * n + j];
   for (int64_t j = 0; j < n; j++) c2[j] -= 2.0 * u21 * c1[j];
-  float* hA = nullptr;
-  if (hipHostMalloc((void**)&hA, (size_t)m * n * 4, hipHostMallocDefault) != hipSuccess) { fprintf(stderr, "host alloc\n"); return 1; }
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < m; i++) {
     for (int64_t j = 0; j < n; j++) {
@@ -131,6 +119,103 @@ int main(int argc, char** argv) {
       hA[(size_t)i * n + j] = (float)x;
     }
   }
+}
+
+static int run_batch(int count, int steps, int warmup, uint64_t seed) {
+  std::vector<tsvd_problem> probs(count);
+  std::vector<std::vector<double>> sv(count);
+  std::vector<void*> bufs;
+  for (int p = 0; p < count; p++) {
+    const double lm = log(1024.0) + (log(65536.0) - log(1024.0)) * ((splitmix(seed * 977 + 4 * p) >> 11) * (1.0 / 9007199254740992.0));
+    const double ln = log(128.0) + (log(4096.0) - log(128.0)) * ((splitmix(seed * 977 + 4 * p + 1) >> 11) * (1.0 / 9007199254740992.0));
+    int64_t m = (int64_t)llround(exp(lm)), n = (int64_t)llround(exp(ln));
+    const int ks[4] = {8, 16, 32, 64};
+    int k = ks[splitmix(seed * 977 + 4 * p + 2) & 3];
+    const bool right = m >= n;
+    const int64_t M = right ? m : n, N = right ? n : m;  // build the tall orientation, transpose if wide
+    const int64_t d = N;
+    if (k > d) k = (int)d;
+    sv[p].resize(d);
+    for (int64_t i = 0; i < d; i++) sv[p][i] = pow(0.95, (double)i);
+    std::vector<float> hT((size_t)M * N);
+    make_known(M, N, sv[p], seed * 131 + p, hT.data());
+    std::vector<float> hA((size_t)m * n);
+    for (int64_t i = 0; i < m; i++)
+      for (int64_t j = 0; j < n; j++) hA[(size_t)i * n + j] = right ? hT[(size_t)i * n + j] : hT[(size_t)j * m + i];
+    std::vector<double> hv0((size_t)k * d);
+    for (size_t i = 0; i < hv0.size(); i++) hv0[i] = gauss(seed * 131 + p + 31, i);
+    float* A; double *v0, *U, *S, *V;
+    if (hipMalloc(&A, (size_t)m * n * 4) || hipMalloc(&v0, hv0.size() * 8) || hipMalloc(&U, (size_t)m * k * 8) ||
+        hipMalloc(&S, (size_t)k * 8) || hipMalloc(&V, (size_t)n * k * 8)) { fprintf(stderr, "device alloc\n"); return 1; }
+    hipMemcpy(A, hA.data(), (size_t)m * n * 4, hipMemcpyHostToDevice);
+    hipMemcpy(v0, hv0.data(), hv0.size() * 8, hipMemcpyHostToDevice);
+    bufs.insert(bufs.end(), {(void*)A, (void*)v0, (void*)U, (void*)S, (void*)V});
+    tsvd_problem& q = probs[p];
+    q = tsvd_problem{};
+    q.A = A; q.dtype = TSVD_F32; q.m = m; q.n = n; q.lda = n;
+    tsvd_opts_default(&q.opts);
+    q.opts.k = k; q.opts.eps = 5e-8; q.opts.gram = TSVD_GRAM_BF16X3; q.opts.v0 = v0;
+    q.U = U; q.ldu = m; q.S = S; q.V = V; q.ldv = n;
+  }
+  tsvd_ctx* ctx;
+  if (tsvd_ctx_create(0, &ctx) != TSVD_OK) { fprintf(stderr, "ctx\n"); return 1; }
+  std::vector<tsvd_info> infos(count);
+  std::vector<std::vector<int>> its(count);
+  for (int p = 0; p < count; p++) { its[p].resize(probs[p].opts.k); infos[p] = tsvd_info{}; infos[p].iters = its[p].data(); }
+  std::vector<int32_t> sts(count);
+  tsvd_status st = TSVD_OK;
+  for (int w = 0; w < warmup; w++) st = tsvd_dense_batched(ctx, count, probs.data(), 0, infos.data(), sts.data(), nullptr);
+  hipDeviceSynchronize();
+  const auto t0 = std::chrono::steady_clock::now();
+  for (int i = 0; i < steps; i++) st = tsvd_dense_batched(ctx, count, probs.data(), 0, infos.data(), sts.data(), nullptr);
+  hipDeviceSynchronize();
+  const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  double err = 0;
+  int ok = 0;
+  long triplets = 0;
+  for (int p = 0; p < count; p++) {
+    const int k = probs[p].opts.k;
+    triplets += k;
+    if (sts[p] != TSVD_OK) continue;
+    ok++;
+    std::vector<double> hS(k);
+    hipMemcpy(hS.data(), probs[p].S, (size_t)k * 8, hipMemcpyDeviceToHost);
+    for (int l = 0; l < k; l++) err = fmax(err, fabs(hS[l] - sv[p][l]) / sv[p][l]);
+  }
+  printf("{\"status\": \"%s\", \"count\": %d, \"ok\": %d, \"steps\": %d, \"ms_per_step\": %.3f, "
+         "\"problems_per_s\": %.2f, \"triplets_per_s\": %.1f, \"gram_ms\": %.3f, \"power_ms\": %.3f, "
+         "\"finish_ms\": %.3f, \"sigma_rel_err_max\": %.3e}\n",
+         tsvd_status_string(st), count, ok, steps, dt * 1e3 / steps, count * steps / dt, triplets * steps / dt,
+         infos[0].t_gram_ms, infos[0].t_eig_ms, infos[0].t_final_ms, err);
+  fflush(stdout);
+  tsvd_ctx_destroy(ctx);
+  for (void* b : bufs) hipFree(b);
+  return ok == count ? 0 : 1;
+}
+
+int main(int argc, char** argv) {
+  if (argc > 1 && argv[1][0] == 'b')
+    return run_batch(argc > 2 ? atoi(argv[2]) : 64, argc > 3 ? atoi(argv[3]) : 3, argc > 4 ? atoi(argv[4]) : 1,
+                     argc > 5 ? strtoull(argv[5], nullptr, 10) : 7);
+  if (argc > 1 && argv[1][0] == 'c')
+    return run_copy(argc > 2 ? strtoull(argv[2], nullptr, 10) : ((size_t)1 << 30), argc > 3 ? atoi(argv[3]) : 5);
+  const int64_t m = argc > 1 ? atoll(argv[1]) : 200000;
+  const int64_t n = argc > 2 ? atoll(argv[2]) : 4096;
+  const int k = argc > 3 ? atoi(argv[3]) : 64;
+  const double eps = argc > 4 ? atof(argv[4]) : 5e-8;
+  const int gram = argc > 5 ? atoi(argv[5]) : TSVD_GRAM_BF16X3;
+  const int steps = argc > 6 ? atoi(argv[6]) : 3;
+  const int warmup = argc > 7 ? atoi(argv[7]) : 1;
+  const uint64_t seed = argc > 8 ? strtoull(argv[8], nullptr, 10) : 7;
+  const size_t copy_bytes = argc > 9 ? strtoull(argv[9], nullptr, 10) : 0;
+  if (copy_bytes > 0 && run_copy(copy_bytes, 1) != 0) return 1;
+  if (m < n || k > n) { fprintf(stderr, "need m >= n >= k\n"); return 2; }
+
+  std::vector<double> s(n);
+  for (int64_t i = 0; i < n; i++) s[i] = pow(0.97, (double)i);
+  float* hA = nullptr;
+  if (hipHostMalloc((void**)&hA, (size_t)m * n * 4, hipHostMallocDefault) != hipSuccess) { fprintf(stderr, "host alloc\n"); return 1; }
+  make_known(m, n, s, seed, hA);
   std::vector<double> hv0((size_t)k * n);
   for (size_t i = 0; i < hv0.size(); i++) hv0[i] = gauss(seed + 31, i);
 

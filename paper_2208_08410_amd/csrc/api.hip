@@ -250,7 +250,7 @@ static tsvd_status run_power(tsvd_ctx* ctx, Bump& bump, void* B, int is_f64, int
     if (hipMemcpyAsync(d_fixed, o->fixed_iters, (size_t)k * 4, hipMemcpyHostToDevice, stream) != hipSuccess)
       return fail(ctx, TSVD_ERR_HIP, "copy fixed_iters");
   }
-  if (hipMemsetAsync(d_status, 0, 16, stream) != hipSuccess) return fail(ctx, TSVD_ERR_HIP, "memset status");
+  if (int rc = zero_bytes_launch(d_status, 16, stream)) return from_internal(ctx, rc, "clear status");
   int rc = power_launch(is_f64, pp, a, stream);
   if (rc == -2) return fail(ctx, TSVD_ERR_UNSUPPORTED, "power kernel does not fit on a CU");
   return from_internal(ctx, rc, "power iteration");
@@ -286,7 +286,7 @@ tsvd_status tsvd_power_gram(tsvd_ctx* ctx, void* B, int32_t dtype, int64_t d, in
   int* d_iters = (int*)bump.take((size_t)k * 4);
   double* d_lambda = (double*)bump.take((size_t)k * 8);
   int* d_fixed = (int*)bump.take((size_t)k * 4);
-  if (hipMemset2DAsync(X, ldx * 8, 0, d * 8, k, stream) != hipSuccess) return fail(ctx, TSVD_ERR_HIP, "memset X");
+  if (int rc = zero_cols_launch(X, ldx, d, k, stream)) return from_internal(ctx, rc, "clear X");
   st = run_power(ctx, bump, B, is_f64, d, ldb, k, o, X, ldx, pp, d_status, d_iters, d_lambda, d_fixed, stream);
   if (st) return st;
   int hs[4];
@@ -420,10 +420,9 @@ static tsvd_status dense_pinned(tsvd_ctx* ctx, const float* A, int64_t m, int64_
 
   hipEventRecord(ctx->ev[0], s);
   if (hipStreamWaitEvent(cs, ctx->ev[0], 0) != hipSuccess) { cleanup(); return fail(ctx, TSVD_ERR_HIP, "wait"); }
-  if (hipMemset2DAsync(U, ldu * 8, 0, m * 8, k, s) != hipSuccess ||
-      hipMemset2DAsync(V, ldv * 8, 0, n * 8, k, s) != hipSuccess || hipMemsetAsync(S, 0, (size_t)k * 8, s) != hipSuccess) {
+  if (zero_cols_launch(U, ldu, m, k, s) || zero_cols_launch(V, ldv, n, k, s) || zero_cols_launch(S, k, k, 1, s)) {
     cleanup();
-    return fail(ctx, TSVD_ERR_HIP, "memset outputs");
+    return fail(ctx, TSVD_ERR_HIP, "clear outputs");
   }
   // ---- pass 1: B = sum_b A_b^T A_b
   for (int64_t b = 0; b < nbatch && !rc; b++) {
@@ -560,10 +559,9 @@ tsvd_status tsvd_dense(tsvd_ctx* ctx, const void* A, int32_t dtype, int32_t loc,
   const int64_t Mw = right ? m : n;
 
   if (hipEventRecord(ctx->ev[0], stream) != hipSuccess) return fail(ctx, TSVD_ERR_HIP, "event");
-  if (hipMemset2DAsync(U, ldu * 8, 0, m * 8, k, stream) != hipSuccess ||
-      hipMemset2DAsync(V, ldv * 8, 0, n * 8, k, stream) != hipSuccess ||
-      hipMemsetAsync(S, 0, (size_t)k * 8, stream) != hipSuccess)
-    return fail(ctx, TSVD_ERR_HIP, "memset outputs");
+  if (zero_cols_launch(U, ldu, m, k, stream) || zero_cols_launch(V, ldv, n, k, stream) ||
+      zero_cols_launch(S, k, k, 1, stream))
+    return fail(ctx, TSVD_ERR_HIP, "clear outputs");
   int rc = syrk_launch(mode, side, A, m, n, lda, sp, partial, B, ldb, 0, stream);
   if (rc) return from_internal(ctx, rc, "gram");
   hipEventRecord(ctx->ev[1], stream);
@@ -798,9 +796,8 @@ tsvd_status tsvd_sparse(tsvd_ctx* ctx, const tsvd_csr* c, const tsvd_opts* o, do
   const int dir1 = right ? 0 : 1, dir2 = right ? 1 : 0;
 
   hipEventRecord(ctx->ev[0], s);
-  if (hipMemset2DAsync(U, ldu * 8, 0, m * 8, k, s) != hipSuccess ||
-      hipMemset2DAsync(V, ldv * 8, 0, n * 8, k, s) != hipSuccess || hipMemsetAsync(S, 0, (size_t)k * 8, s) != hipSuccess)
-    return fail(ctx, TSVD_ERR_HIP, "memset outputs");
+  if (zero_cols_launch(U, ldu, m, k, s) || zero_cols_launch(V, ldv, n, k, s) || zero_cols_launch(S, k, k, 1, s))
+    return fail(ctx, TSVD_ERR_HIP, "clear outputs");
   hipEventRecord(ctx->ev[1], s);
   std::vector<int> iters(k, 0);
   std::vector<double> lams(k, 0.0);

@@ -281,15 +281,13 @@ tsvd_status batch_enqueue(tsvd_ctx* ctx, const tsvd_problem* probs, BatchPlan& b
   if (ev && hipEventRecord(ev[0], stream) != hipSuccess) return fail(ctx, TSVD_ERR_HIP, "event");
   if (hipMemcpyAsync(bbase, h, bp.desc_bytes, hipMemcpyHostToDevice, stream) != hipSuccess)
     return fail(ctx, TSVD_ERR_HIP, "copy descriptors");
-  if (hipMemsetAsync(d_status, 0, (size_t)count * 16, stream) != hipSuccess)
-    return fail(ctx, TSVD_ERR_HIP, "memset status");
-  for (int i = 0; i < count; i++) {
-    const tsvd_problem& q = probs[i];
-    const ProbPlan& p = bp.P[i];
-    if (hipMemset2DAsync(q.U, q.ldu * 8, 0, q.m * 8, p.k, stream) != hipSuccess ||
-        hipMemset2DAsync(q.V, q.ldv * 8, 0, q.n * 8, p.k, stream) != hipSuccess ||
-        hipMemsetAsync(q.S, 0, (size_t)p.k * 8, stream) != hipSuccess)
-      return fail(ctx, TSVD_ERR_HIP, "memset outputs of problem %d", i);
+  if (int rc = zero_bytes_launch(d_status, (size_t)count * 16, stream)) return from_internal(ctx, rc, "clear status");
+  {
+    // every problem's U, V and S, one launch per side group
+    const FinishJob* dfj0 = (const FinishJob*)(bbase + bp.off_fjobs);
+    int rc = finish_grouped_zero_launch(dfj0, bp.fcount[0], bp.fcols[0], stream);
+    if (!rc) rc = finish_grouped_zero_launch(dfj0 + bp.fcount[0], bp.fcount[1], bp.fcols[1], stream);
+    if (rc) return from_internal(ctx, rc, "clear outputs");
   }
   for (auto& g : bp.ggroups) {
     const int rc = syrk_grouped_launch(g.mode, g.side, (const GramJob*)(bbase + bp.off_gjobs) + g.first, g.count,

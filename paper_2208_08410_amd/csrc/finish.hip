@@ -322,6 +322,56 @@ __global__ __launch_bounds__(256) void finish_grouped_apply_kernel(const FinishJ
   else apply_column(j.V, j.ldv, j.n, j.U, j.ldu, j.m, fac, c, blockIdx.x);
 }
 
+// Zero fills.  The library clears device memory with these kernels rather
+// than with runtime memsets, so that the work it puts on a caller's stream is
+// kernels only (memset nodes recorded into a captured graph have given wrong
+// results on replays here).
+__global__ __launch_bounds__(256) void zero_cols_kernel(double* p, int64_t ld, int64_t rows, int64_t cols) {
+  for (int64_t c = blockIdx.y; c < cols; c += gridDim.y)
+    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < rows; r += (int64_t)gridDim.x * 256) p[c * ld + r] = 0.0;
+}
+
+__global__ __launch_bounds__(256) void zero_words32_kernel(uint32_t* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = 0u;
+}
+
+int zero_cols_launch(double* p, int64_t ld, int64_t rows, int64_t cols, hipStream_t s) {
+  if (!p || rows <= 0 || cols <= 0) return 0;
+  const unsigned gx = (unsigned)std::min<int64_t>((rows + 255) / 256, 64);
+  const unsigned gy = (unsigned)std::min<int64_t>(cols, 4096);
+  hipLaunchKernelGGL(zero_cols_kernel, dim3(gx, gy), dim3(256), 0, s, p, ld, rows, cols);
+  TSVD_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int zero_bytes_launch(void* p, size_t bytes, hipStream_t s) {
+  if (!p || bytes == 0) return 0;
+  const int64_t n = (int64_t)((bytes + 3) / 4);  // callers pass multiples of 4 bytes
+  hipLaunchKernelGGL(zero_words32_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 4096)), dim3(256), 0, s,
+                     (uint32_t*)p, n);
+  TSVD_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+// U[:, c], V[:, c] and S[c] of every column c of every job (grid: the group's
+// columns), so that columns a problem does not produce read as zero.
+__global__ __launch_bounds__(256) void finish_grouped_zero_kernel(const FinishJob* jobs, int njobs) {
+  const FinishJob& j = jobs[find_fjob(jobs, njobs, blockIdx.x, 1)];
+  const int64_t c = (int64_t)blockIdx.x - j.cbegin;
+  double* u = j.U + c * j.ldu;
+  double* v = j.V + c * j.ldv;
+  for (int64_t r = threadIdx.x; r < j.m; r += 256) u[r] = 0.0;
+  for (int64_t r = threadIdx.x; r < j.n; r += 256) v[r] = 0.0;
+  if (threadIdx.x == 0) j.S[c] = 0.0;
+}
+
+int finish_grouped_zero_launch(const FinishJob* d_jobs, int njobs, int64_t cols, hipStream_t s) {
+  if (njobs <= 0 || cols <= 0) return 0;
+  hipLaunchKernelGGL(finish_grouped_zero_kernel, dim3((unsigned)cols), dim3(256), 0, s, d_jobs, njobs);
+  TSVD_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
 int finish_grouped_launch(int side, const FinishJob* d_jobs, int njobs, int64_t units, int64_t cols, int64_t max_rows,
                           hipStream_t s) {
   if (njobs <= 0) return 0;

@@ -99,6 +99,10 @@ struct FinishJob {
   int64_t cbegin;        // first workgroup in the scale launch (k units)
 };
 // max_rows: the longest U or V column among the jobs (rows of the apply grid)
+// zero fills (kernels, not runtime memsets)
+int zero_cols_launch(double* p, int64_t ld, int64_t rows, int64_t cols, hipStream_t s);
+int zero_bytes_launch(void* p, size_t bytes, hipStream_t s);
+int finish_grouped_zero_launch(const FinishJob* d_jobs, int njobs, int64_t cols, hipStream_t s);
 int finish_grouped_launch(int side, const FinishJob* d_jobs, int njobs, int64_t units, int64_t cols, int64_t max_rows,
                           hipStream_t s);
 // row tiles of the finishing product; workspace = (tiles + 2) * k doubles:

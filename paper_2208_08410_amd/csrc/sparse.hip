@@ -246,7 +246,7 @@ static int grid_for(int64_t work, int per_block, int cap = 1 << 20) {
 
 int csr_validate(const int64_t* rowptr, const int32_t* col, int64_t m, int64_t n, int64_t nnz, int* d_bad,
                  hipStream_t s) {
-  TSVD_HIP_TRY(hipMemsetAsync(d_bad, 0, sizeof(int), s));
+  if (int rc = zero_bytes_launch(d_bad, sizeof(int), s)) return rc;
   hipLaunchKernelGGL(csr_validate_kernel, dim3(grid_for(m > nnz ? m : nnz, 256, 65536)), dim3(256), 0, s, rowptr,
                      col, m, n, nnz, d_bad);
   TSVD_HIP_TRY(hipGetLastError());
@@ -276,7 +276,7 @@ int csc_build(const int64_t* rowptr, const int32_t* col, const float* val, int64
   unsigned long long* fill = cnt + (n + 1);
   unsigned long long* bsum = fill + (n + 1);
   const int64_t nb = (n + SCAN_B - 1) / SCAN_B;
-  TSVD_HIP_TRY(hipMemsetAsync(cnt, 0, (size_t)(n + 1) * 8 * 2, s));
+  if (int rc = zero_bytes_launch(cnt, (size_t)(n + 1) * 8 * 2, s)) return rc;
   hipLaunchKernelGGL(csc_count_kernel, dim3(grid_for(nnz, 256, 65536)), dim3(256), 0, s, col, nnz, cnt);
   hipLaunchKernelGGL(scan_block_sums_kernel, dim3((unsigned)nb), dim3(256), 0, s, cnt, n, bsum);
   hipLaunchKernelGGL(scan_bsums_kernel, dim3(1), dim3(64), 0, s, bsum, nb);

@@ -84,10 +84,12 @@ def test_nonfinite_gram(ctx):
     assert e.value.status == P.NONFINITE
 
 
-@pytest.mark.parametrize("d,k", [(3999, 3), (4096, 3), (6000, 2)])
+@pytest.mark.parametrize("d,k", [(3999, 3), (4096, 3), (6000, 2), (9001, 2)])
 def test_power_fp32_register_rows(ctx, d, k):
-    """Large d: a block's rows are split over LDS, registers and HBM; the
-    result must match the FP64 oracle run for the same number of steps."""
+    """Large d: a block's rows are split over LDS, registers and HBM (d = 9001:
+    no register rows, most rows streamed from HBM, and an odd leading dimension
+    that takes the scalar load and deflation paths); the result must match the
+    FP64 oracle run for the same number of steps."""
     g = synth.rng(d, 3)
     lam = 0.8 ** np.arange(d, dtype=np.float64)
     Q = synth.haar_orthonormal(d, 8, seed=d, tag=1)
