@@ -129,7 +129,7 @@ typedef struct {
   int32_t power_blocks;  /* workgroups of the power-iteration launch: 0 = one per CU */
   int32_t team_kib;      /* batched power launch: KiB of a problem's Gram per team workgroup, which
                             sets the team size (ceil(4 d^2 / (team_kib * 1024)) workgroups);
-                            0 = 512; range [8, 65536] */
+                            0 = 256; range [8, 65536] */
   int32_t group_kchunk;  /* batched Gram: contraction rows per work unit; 0 = 2048; range [32, 2^20] */
   int32_t sparse_row_bits; /* sparse products: tiles of 2^bits rows (0 = library choice, about 2 row
                               chunks per CU, 32..8192 rows); range [0, 13]; applies to handles created

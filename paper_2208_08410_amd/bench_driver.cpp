@@ -8,7 +8,7 @@
 //   tsvd_bench copy BYTES [reps]
 //     a plain device-to-device copy kernel of BYTES (multiple of 16), the
 //     reference for scaling hardware traffic counters to bytes
-//   tsvd_bench batch COUNT [steps warmup seed]
+//   tsvd_bench batch COUNT [steps warmup seed team_kib]
 //     COUNT problems of the serving mix (m log-uniform in [1024, 65536], n in
 //     [128, 4096], k in {8, 16, 32, 64}, s_i = 0.95^i, eps = 5e-8) solved by
 //     one tsvd_dense_batched call per step, A resident in HBM
@@ -121,7 +121,7 @@ static void make_known(int64_t m, int64_t n, const std::vector<double>& s, uint6
   }
 }
 
-static int run_batch(int count, int steps, int warmup, uint64_t seed) {
+static int run_batch(int count, int steps, int warmup, uint64_t seed, int team_kib) {
   std::vector<tsvd_problem> probs(count);
   std::vector<std::vector<double>> sv(count);
   std::vector<void*> bufs;
@@ -159,6 +159,11 @@ static int run_batch(int count, int steps, int warmup, uint64_t seed) {
   }
   tsvd_ctx* ctx;
   if (tsvd_ctx_create(0, &ctx) != TSVD_OK) { fprintf(stderr, "ctx\n"); return 1; }
+  if (team_kib > 0) {
+    tsvd_tuning tu = {};
+    tu.team_kib = team_kib;
+    if (tsvd_ctx_set_tuning(ctx, &tu) != TSVD_OK) { fprintf(stderr, "tuning\n"); return 2; }
+  }
   std::vector<tsvd_info> infos(count);
   std::vector<std::vector<int>> its(count);
   for (int p = 0; p < count; p++) { its[p].resize(probs[p].opts.k); infos[p] = tsvd_info{}; infos[p].iters = its[p].data(); }
@@ -182,10 +187,10 @@ static int run_batch(int count, int steps, int warmup, uint64_t seed) {
     hipMemcpy(hS.data(), probs[p].S, (size_t)k * 8, hipMemcpyDeviceToHost);
     for (int l = 0; l < k; l++) err = fmax(err, fabs(hS[l] - sv[p][l]) / sv[p][l]);
   }
-  printf("{\"status\": \"%s\", \"count\": %d, \"ok\": %d, \"steps\": %d, \"ms_per_step\": %.3f, "
+  printf("{\"status\": \"%s\", \"count\": %d, \"team_kib\": %d, \"ok\": %d, \"steps\": %d, \"ms_per_step\": %.3f, "
          "\"problems_per_s\": %.2f, \"triplets_per_s\": %.1f, \"gram_ms\": %.3f, \"power_ms\": %.3f, "
          "\"finish_ms\": %.3f, \"sigma_rel_err_max\": %.3e}\n",
-         tsvd_status_string(st), count, ok, steps, dt * 1e3 / steps, count * steps / dt, triplets * steps / dt,
+         tsvd_status_string(st), count, team_kib, ok, steps, dt * 1e3 / steps, count * steps / dt, triplets * steps / dt,
          infos[0].t_gram_ms, infos[0].t_eig_ms, infos[0].t_final_ms, err);
   fflush(stdout);
   tsvd_ctx_destroy(ctx);
@@ -196,7 +201,7 @@ static int run_batch(int count, int steps, int warmup, uint64_t seed) {
 int main(int argc, char** argv) {
   if (argc > 1 && argv[1][0] == 'b')
     return run_batch(argc > 2 ? atoi(argv[2]) : 64, argc > 3 ? atoi(argv[3]) : 3, argc > 4 ? atoi(argv[4]) : 1,
-                     argc > 5 ? strtoull(argv[5], nullptr, 10) : 7);
+                     argc > 5 ? strtoull(argv[5], nullptr, 10) : 7, argc > 6 ? atoi(argv[6]) : 0);
   if (argc > 1 && argv[1][0] == 'c')
     return run_copy(argc > 2 ? strtoull(argv[2], nullptr, 10) : ((size_t)1 << 30), argc > 3 ? atoi(argv[3]) : 5);
   const int64_t m = argc > 1 ? atoll(argv[1]) : 200000;

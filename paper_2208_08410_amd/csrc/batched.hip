@@ -50,9 +50,9 @@ double team_cost(int64_t d, int k, int g) { return (double)k * std::max((double)
 }  // namespace
 
 tsvd_status batch_plan(tsvd_ctx* ctx, int count, const tsvd_problem* probs, BatchPlan& bp) {
-  // default: 512 KiB of the problem's Gram per member (small teams, many
-  // problems at once; a member's rows that do not fit in LDS stream from L2)
-  const int team_kib = ctx->tuning.team_kib > 0 ? ctx->tuning.team_kib : 512;
+  // default: 256 KiB of the problem's Gram per member, about what a member
+  // holds on chip (LDS rows plus register rows) up to a dimension of 8192
+  const int team_kib = ctx->tuning.team_kib > 0 ? ctx->tuning.team_kib : 256;
   const int64_t kc_target = ctx->tuning.group_kchunk > 0 ? ctx->tuning.group_kchunk : 2048;
   bp.count = count;
   bp.P.assign(count, ProbPlan());

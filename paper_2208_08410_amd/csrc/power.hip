@@ -685,6 +685,15 @@ __device__ __forceinline__ int solve_problem(const PowerArgs& a, int b, int G, u
   return err;
 }
 
+// Out-of-line entry into solve_problem for the batched kernel: each register
+// variant keeps its own register allocation (inlined together they spill);
+// the call's register saves happen once per problem, not per iteration.
+template <typename BT, int NV, int RR>
+__device__ __attribute__((noinline)) int solve_problem_call(const PowerArgs& a, int b, int G, unsigned char* smem,
+                                                            uint32_t* epoch, uint32_t* nx, uint32_t* np) {
+  return solve_problem<BT, NV, RR>(a, b, G, smem, *epoch, *nx, *np);
+}
+
 // Single problem: the whole grid is one team.
 template <typename BT, int NV, int RR>
 __global__ __launch_bounds__(256, 1) void power_kernel(PowerArgs a) {
@@ -739,7 +748,15 @@ __global__ __launch_bounds__(256, 1) void power_dyn_kernel(const PowerArgs* prob
       continue;
     }
     uint32_t epoch = 0, nx = 0, np = 0;
-    solve_problem<float, 0, 0>(a, rank, gsize[h], smem, epoch, nx, np);
+    // the problem's register-row variant (as the single-problem launch picks
+    // it): up to 2-4 rows per wave held in registers when the Gram dimension
+    // allows, the rest of the member's rows in LDS and then HBM
+    const int d = a.d;
+    if (d <= 1024) solve_problem_call<float, 4, 4>(a, rank, gsize[h], smem, &epoch, &nx, &np);
+    else if (d <= 2048) solve_problem_call<float, 8, 4>(a, rank, gsize[h], smem, &epoch, &nx, &np);
+    else if (d <= 4096) solve_problem_call<float, 16, 2>(a, rank, gsize[h], smem, &epoch, &nx, &np);
+    else if (d <= 8192) solve_problem_call<float, 32, 1>(a, rank, gsize[h], smem, &epoch, &nx, &np);
+    else solve_problem_call<float, 0, 0>(a, rank, gsize[h], smem, &epoch, &nx, &np);
     __syncthreads();
   }
 }
