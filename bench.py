@@ -26,6 +26,7 @@ import argparse
 import json
 import math
 import os
+import subprocess
 import sys
 import time
 
@@ -94,6 +95,18 @@ def source_hash(key: str) -> str:
     if marker:
         text = text[:text.index(marker)]
     return hashlib.sha256(text.encode()).hexdigest()[:16]
+
+
+def measured_mfma():
+    """Dense MFMA rates of this GPU from the C++ driver's peak loops (every CU,
+    four independent chains per wave), or None when the driver is not built."""
+    exe = os.path.join(ROOT, "paper_2208_08410_amd", "tsvd_bench")
+    if not os.path.exists(exe):
+        return None
+    r = subprocess.run([exe, "mfma"], capture_output=True, text=True, timeout=120)
+    if r.returncode != 0:
+        return None
+    return json.loads(r.stdout.strip().splitlines()[-1])
 
 
 def measured_traffic(kernel: str):
@@ -756,6 +769,12 @@ def main():
         best = min(best, e0.elapsed_time(e1))
     out["hbm_copy_gbs_measured"] = 2 * src.numel() * 4 / (best * 1e-3) / 1e9
     del src, dst
+    # measured dense MFMA rates (the C++ driver's peak loops, run as a child process)
+    mm = measured_mfma()
+    if mm:
+        out["mfma_measured"] = mm
+        if a.gram == "bf16x3":
+            roof_gram["frac_of_measured_peak"] = roof_gram["achieved"] / mm["mfma_bf16_tflops"]
     if a.cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, s, a.k, a.eps, a.seed)
     ctx.close()

@@ -8,6 +8,9 @@
 //   tsvd_bench copy BYTES [reps]
 //     a plain device-to-device copy kernel of BYTES (multiple of 16), the
 //     reference for scaling hardware traffic counters to bytes
+//   tsvd_bench mfma
+//     dense MFMA peak loops on every CU (BF16 32x32x16 and FP64 16x16x4, four
+//     independent accumulators per wave): the measured roofline denominators
 //   tsvd_bench batch COUNT [steps warmup seed team_kib]
 //     COUNT problems of the serving mix (m log-uniform in [1024, 65536], n in
 //     [128, 4096], k in {8, 16, 32, 64}, s_i = 0.95^i, eps = 5e-8) solved by
@@ -43,6 +46,76 @@ static double gauss(uint64_t seed, uint64_t i) {  // Box-Muller on two counter d
 __global__ void copy_kernel(const float4* __restrict__ src, float4* __restrict__ dst, size_t n) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
     dst[i] = src[i];
+}
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float floatx16_t __attribute__((ext_vector_type(16)));
+typedef double doublex4_t __attribute__((ext_vector_type(4)));
+
+// ITERS x 4 independent MFMA chains per wave; the results are stored so the
+// work is not removed
+template <int ITERS>
+__global__ __launch_bounds__(256) void mfma_bf16_loop(float* out, float seed) {
+  bf16x8_t a, b;
+  for (int i = 0; i < 8; i++) { a[i] = (__bf16)(seed + 0.001f * threadIdx.x); b[i] = (__bf16)(seed - 0.002f * i); }
+  floatx16_t c0 = {}, c1 = {}, c2 = {}, c3 = {};
+  for (int it = 0; it < ITERS; it++) {
+    c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c0, 0, 0, 0);
+    c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c1, 0, 0, 0);
+    c2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c2, 0, 0, 0);
+    c3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c3, 0, 0, 0);
+  }
+  float s = 0;
+  for (int e = 0; e < 16; e++) s += c0[e] + c1[e] + c2[e] + c3[e];
+  out[blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
+template <int ITERS>
+__global__ __launch_bounds__(256) void mfma_f64_loop(double* out, double seed) {
+  const double a = seed + 0.001 * threadIdx.x, b = seed - 0.002;
+  doublex4_t c0 = {}, c1 = {}, c2 = {}, c3 = {};
+  for (int it = 0; it < ITERS; it++) {
+    c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c0, 0, 0, 0);
+    c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c1, 0, 0, 0);
+    c2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c2, 0, 0, 0);
+    c3 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c3, 0, 0, 0);
+  }
+  out[blockIdx.x * blockDim.x + threadIdx.x] = c0[0] + c1[1] + c2[2] + c3[3];
+}
+
+static int run_mfma() {
+  int num_cu = 0;
+  if (hipDeviceGetAttribute(&num_cu, hipDeviceAttributeMultiprocessorCount, 0) != hipSuccess) return 1;
+  const int grid = num_cu * 8;  // 8 workgroups of 4 waves per CU: 8 waves per SIMD
+  constexpr int ITERS = 4096;
+  void* out;
+  if (hipMalloc(&out, (size_t)grid * 256 * 8) != hipSuccess) return 1;
+  hipEvent_t e0, e1;
+  hipEventCreate(&e0); hipEventCreate(&e1);
+  float best_bf16 = 1e30f, best_f64 = 1e30f;
+  for (int r = 0; r < 4; r++) {
+    hipEventRecord(e0, nullptr);
+    hipLaunchKernelGGL(mfma_bf16_loop<ITERS>, dim3(grid), dim3(256), 0, nullptr, (float*)out, 1.0f + r);
+    hipEventRecord(e1, nullptr);
+    hipEventSynchronize(e1);
+    float t;
+    hipEventElapsedTime(&t, e0, e1);
+    if (r > 0 && t < best_bf16) best_bf16 = t;
+    hipEventRecord(e0, nullptr);
+    hipLaunchKernelGGL(mfma_f64_loop<ITERS>, dim3(grid), dim3(256), 0, nullptr, (double*)out, 1.0 + r);
+    hipEventRecord(e1, nullptr);
+    hipEventSynchronize(e1);
+    hipEventElapsedTime(&t, e0, e1);
+    if (r > 0 && t < best_f64) best_f64 = t;
+  }
+  const double waves = (double)grid * 4;
+  const double bf16_flops = waves * ITERS * 4 * (2.0 * 32 * 32 * 16);
+  const double f64_flops = waves * ITERS * 4 * (2.0 * 16 * 16 * 4);
+  printf("{\"mfma_bf16_tflops\": %.1f, \"mfma_f64_tflops\": %.2f, \"cus\": %d}\n", bf16_flops / (best_bf16 * 1e-3) / 1e12,
+         f64_flops / (best_f64 * 1e-3) / 1e12, num_cu);
+  fflush(stdout);
+  hipFree(out);
+  return 0;
 }
 
 static int run_copy(size_t bytes, int reps) {
@@ -199,6 +272,7 @@ static int run_batch(int count, int steps, int warmup, uint64_t seed, int team_k
 }
 
 int main(int argc, char** argv) {
+  if (argc > 1 && argv[1][0] == 'm') return run_mfma();
   if (argc > 1 && argv[1][0] == 'b')
     return run_batch(argc > 2 ? atoi(argv[2]) : 64, argc > 3 ? atoi(argv[3]) : 3, argc > 4 ? atoi(argv[4]) : 1,
                      argc > 5 ? strtoull(argv[5], nullptr, 10) : 7, argc > 6 ? atoi(argv[6]) : 0);
