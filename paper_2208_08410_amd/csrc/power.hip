@@ -187,11 +187,14 @@ __device__ __forceinline__ bool allreduce_blocks(uint64_t* pbuf, int pw, int b, 
   __syncthreads();
   for (int jb = 0; jb < P; jb += 256) {
     const int Pc = min(256, P - jb);
-    const int NG = 256 / Pc;
-    const int j = tid % Pc, gg = tid / Pc;
+    // thread (gg, j) = (tid / Pp, tid % Pp) with Pp the power of two >= Pc:
+    // it sums output j over the workgroups g = gg, gg + NG, ...
+    const int lg = Pc > 1 ? 32 - __clz(Pc - 1) : 0;
+    const int Pp = 1 << lg, NG = 256 >> lg;
+    const int j = tid & (Pp - 1), gg = tid >> lg;
     double acc = 0.0;
     bool ok = true;
-    if (gg < NG) {
+    if (j < Pc) {
       int64_t budget = spin_limit;
       for (int g0 = gg; g0 < G && ok; g0 += NG * 8) {
         uint64_t lo[8], hi[8];
@@ -230,13 +233,19 @@ __device__ __forceinline__ bool allreduce_blocks(uint64_t* pbuf, int pw, int b, 
             if (g0 + NG * u < G) acc += ll_join_f64(lo[u], hi[u]);
         }
       }
-      scratch[gg * Pc + j] = acc;
     }
     if (!ok) *flag = 0;
+    // fixed-order tree over gg: a butterfly across the lanes of a wave that
+    // hold the same j (Pp, 2 Pp, ... apart), then the per-wave partials (or,
+    // for Pp >= 64, the per-group ones) in order
+    for (int m = Pp; m < 64; m <<= 1) acc += __shfl_xor(acc, m, 64);
+    const int nparts = Pp < 64 ? 4 : NG;
+    const int part = Pp < 64 ? (tid >> 6) : gg;
+    if (j < Pc && (Pp >= 64 || (tid & 63) < Pp)) scratch[part * Pp + j] = acc;
     __syncthreads();
     if (tid < Pc) {
       double s = 0.0;
-      for (int g = 0; g < NG; g++) s += scratch[g * Pc + tid];
+      for (int q = 0; q < nparts; q++) s += scratch[q * Pp + tid];
       out[jb + tid] = s;
     }
     __syncthreads();
@@ -603,19 +612,27 @@ __device__ __forceinline__ int solve_problem(const PowerArgs& a, int b, int G, u
       }
     }
     __syncthreads();
-    {
-      double s = 0.0;
-      for (int i = tid; i < nrows; i += 256) s = fma(vv[i], vv[i], s);
-      s = block_sum(s, redw, tid, 256);
-      if (tid == 0) sv[2] = s;
-      __syncthreads();
-    }
+
+    // ---- publish v' = v - X c (own rows) with the block partial ||v'_R||^2:
+    // one wait brings every block v' (the GEMV input of the deflation) and
+    // ||v'||^2; 1 / ||v'|| is then applied to the row sums and coefficients
+    constexpr int WG = (NV <= 16) ? 16 : 8;  // gather width (registers permitting)
     ++epoch;
+    const uint32_t vep = epoch;
+    uint64_t* vb = a.vex + (int64_t)(l & 1) * a.vstride;
+    double vn2;
     {
       uint64_t* pb = a.pex + (int64_t)(np & 1) * G * a.pw; np++;
-      if (!allreduce_blocks(pb, a.pw, b, G, epoch, sv + 2, 1, st + 4, scratch, flag, a.spin_limit)) { err = ERR_SPIN; break; }
+      publish_rows<BT>(vb, vep, r0, nrows, vv);
+      if (wave == 3) {
+        double q = 0.0;
+        for (int i = lane; i < nrows; i += 64) q = fma(vv[i], vv[i], q);
+        q = wave_sum(q);
+        if (lane < 4) ll_store(pb + 4 * (int64_t)b + lane, vep, f64_half(lane < 2 ? q : 0.0, lane & 1));
+      }
+      double d0;
+      if (!gather_iteration<BT, WG>(vb, pb, vep, d, b, G, xs, redw, flag, a.spin_limit, vn2, d0)) { err = ERR_SPIN; break; }
     }
-    const double vn2 = st[4];
     if (!isfinite(vn2)) { err = ERR_NONFINITE; break; }
     if (!(vn2 > 0.0)) { rankdef = true; kdone = l; break; }
     const double vinv = 1.0 / sqrt(vn2);
@@ -627,52 +644,45 @@ __device__ __forceinline__ int solve_problem(const PowerArgs& a, int b, int G, u
     __syncthreads();
     if (l + 1 >= a.k) break;
 
-    // ---- deflation: w = B v, alpha = v.w, B <- B - v w^T - w v^T + alpha v v^T
-    // v and w travel as B's type (the GEMV and the update read them as such)
-    constexpr int WG = (NV <= 16) ? 16 : 8;  // gather width (registers permitting)
-    ++epoch;
-    uint64_t* vb = a.vex + (int64_t)(l & 1) * a.vstride;
-    publish_rows<BT>(vb, epoch, r0, nrows, vv);
-    {
-      double q0, d0;
-      if (!gather_iteration<BT, WG>(vb, vb, epoch, d, b, 0, xs, redw, flag, a.spin_limit, q0, d0)) { err = ERR_SPIN; break; }
-    }
-    gemv_regrows<BT, NV, RR>(R, cr, nreg, xs, 1.0, wv);
-    gemv_range<BT, 4>(Bs, a.ldsB, 0, cr, xs, d, true, 1.0, wv);
-    gemv_range<BT, (RR > 0 ? 2 : 8)>(Bg, a.ldb, g0, nrows, xs, d, a.vec_ok != 0, 1.0, wv);
+    // ---- deflation: w = B v, alpha = v.w, B <- B - v w^T - beta v^T with
+    // beta = w - alpha v (= (I - v v^T) B (I - v v^T)); xs holds v' = v ||v'||
+    gemv_regrows<BT, NV, RR>(R, cr, nreg, xs, vinv, wv);
+    gemv_range<BT, 4>(Bs, a.ldsB, 0, cr, xs, d, true, vinv, wv);
+    gemv_range<BT, (RR > 0 ? 2 : 8)>(Bg, a.ldb, g0, nrows, xs, d, a.vec_ok != 0, vinv, wv);
     __syncthreads();
-    if (tid == 0) {
-      double al = 0.0;
-      for (int i = 0; i < nrows; i++) al = fma(vv[i], wv[i], al);
-      sv[3] = al;
-    }
-    __syncthreads();
+    // publish w (own rows) with the block partial alpha_R = v_R . w_R
     ++epoch;
     const uint32_t wep = epoch;
     uint64_t* wb = a.wex + (int64_t)(l & 1) * a.vstride;
-    publish_rows<BT>(wb, wep, r0, nrows, wv);
+    double alpha;
     {
       uint64_t* pb = a.pex + (int64_t)(np & 1) * G * a.pw; np++;
-      if (!allreduce_blocks(pb, a.pw, b, G, epoch, sv + 3, 1, st + 5, scratch, flag, a.spin_limit)) { err = ERR_SPIN; break; }
+      publish_rows<BT>(wb, wep, r0, nrows, wv);
+      if (wave == 3) {
+        double q = 0.0;
+        for (int i = lane; i < nrows; i += 64) q = fma(vv[i], wv[i], q);
+        q = wave_sum(q);
+        if (lane < 4) ll_store(pb + 4 * (int64_t)b + lane, wep, f64_half(lane < 2 ? q : 0.0, lane & 1));
+      }
+      double d0;
+      if (!gather_iteration<BT, WG>(wb, pb, wep, d, b, G, xs, redw, flag, a.spin_limit, alpha, d0)) { err = ERR_SPIN; break; }
     }
-    const double alpha = st[5];
-    // Own-row update B <- B - beta v^T - v w^T with beta = w - alpha v, in two
-    // phases that each read one vector from LDS: first with xs = v, then with
-    // xs = w (gathered from the published words).  Each phase is done in FP64
-    // and rounded to B's type.
-    for (int i = tid; i < nrows; i += 256) xv[i] = wv[i] - alpha * vv[i];  // beta (own rows)
-    __syncthreads();
-    deflate_rows<BT>(Bs, a.ldsB, 0, cr, true, d, xs, xv);
-    deflate_regrows<BT, NV, RR>(R, cr, nreg, d, xs, xv);
-    deflate_rows<BT>(Bg, a.ldb, g0, nrows, a.vec_ok != 0, d, xs, xv);
-    __syncthreads();
-    {
-      double q0, d0;
-      if (!gather_iteration<BT, WG>(wb, wb, wep, d, b, 0, xs, redw, flag, a.spin_limit, q0, d0)) { err = ERR_SPIN; break; }
-    }
+    // Own-row update in two phases that each read one vector from LDS, each
+    // done in FP64 and rounded to B's type: first B -= v w^T with xs = w, then
+    // B -= beta v^T with xs = v' read again from its published words (beta is
+    // scaled by 1 / ||v'||)
     deflate_rows<BT>(Bs, a.ldsB, 0, cr, true, d, xs, vv);
     deflate_regrows<BT, NV, RR>(R, cr, nreg, d, xs, vv);
     deflate_rows<BT>(Bg, a.ldb, g0, nrows, a.vec_ok != 0, d, xs, vv);
+    for (int i = tid; i < nrows; i += 256) xv[i] = (wv[i] - alpha * vv[i]) * vinv;
+    __syncthreads();
+    {
+      double q0, d0;
+      if (!gather_iteration<BT, WG>(vb, vb, vep, d, b, 0, xs, redw, flag, a.spin_limit, q0, d0)) { err = ERR_SPIN; break; }
+    }
+    deflate_rows<BT>(Bs, a.ldsB, 0, cr, true, d, xs, xv);
+    deflate_regrows<BT, NV, RR>(R, cr, nreg, d, xs, xv);
+    deflate_rows<BT>(Bg, a.ldb, g0, nrows, a.vec_ok != 0, d, xs, xv);
     __syncthreads();
   }
 
