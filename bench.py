@@ -81,9 +81,10 @@ def parse():
 
 
 TRAFFIC_SOURCES = {
-    # key -> (file under csrc/, marker that starts its host-side part, or None for the whole file)
-    "power.hip-device": ("power.hip", "// Host side"),
-    "syrk.hip-device": ("syrk.hip", "// Host launchers"),
+    # key -> (file under csrc/, marker that ends the hashed part, or None for the
+    # whole file); whole files, since the host-side plans set the launch shapes
+    "power.hip": ("power.hip", None),
+    "syrk.hip": ("syrk.hip", None),
     "common.h": ("common.h", None),
 }
 
