@@ -113,7 +113,7 @@ def measured_mfma():
 def measured_traffic(kernel: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary (FETCH_SIZE, WRITE_SIZE scaled by a reference copy), or None when
-    the device source the kernel is built from has changed since the counters
+    a source file the kernel is built or planned from has changed since the counters
     were taken."""
     path = os.path.join(ROOT, "profiles", "traffic_power_gram_finish_dense_200000x4096_k64.txt")
     try:
