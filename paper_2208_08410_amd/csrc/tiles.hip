@@ -121,8 +121,10 @@ __global__ __launch_bounds__(TW * 64) void spmv_tiles_kernel(const int64_t* tptr
     double left = 0.0;   // the first segment's sum, held by the one lane that closed it
     // UC chunks of 64 entries per step: their keys, values and x gathers are
     // all issued before the first scan, so each wave keeps UC independent
-    // gathers in flight; the chunks are then reduced in order
-    constexpr int UC = 4;
+    // gathers in flight; the chunks are then reduced in order.  With 8, a
+    // wave's share of a tile at density 1e-6 (about 270 entries) takes one
+    // step instead of two (A x at 5e7 x 5e7: 27.1 -> 25.2 ms; 5 does as well)
+    constexpr int UC = 8;
     for (int64_t s0 = wa; s0 < wb; s0 += 64 * UC) {
       uint32_t kk[UC];
       float vv[UC];
