@@ -90,6 +90,32 @@ def test_zero_matrix_rank_deficient(ctx):
     assert np.all(S == 0) and np.all(U == 0) and np.all(V == 0)
 
 
+@pytest.mark.parametrize("gram", ["bf16x3", "fp32"])
+def test_rank_below_k_keeps_v_orthonormal(ctx, gram):
+    """A of exact rank 3 (FP32, 1500 x 300, s = 3, 2, 1) asked for k = 6 with
+    200 fixed iterations per triplet.  The first three triplets meet the
+    closed form; after them the deflated Gram is at rounding level, so the
+    later triplets have sigma at that level, while V stays orthonormal to
+    FP64 rounding (each v is re-orthogonalised against the earlier ones and
+    normalised through the gather that carries its norm) and U stays finite.
+    A rank-deficiency stop after the third triplet is also a valid outcome."""
+    m, n, k = 1500, 300, 6
+    s = np.zeros(n)
+    s[:3] = [3.0, 2.0, 1.0]
+    dk = synth.dense_known(m, n, s, seed=5, dtype=np.float32)
+    st = synth.start_vectors(k, n, seed=21)
+    U, S, V, info = run(ctx, dk.A, k, 1e-8, st, fixed_iters=[200] * k, gram=gram)
+    assert info["status"] == "TSVD_OK"
+    kd = info["k_done"]
+    assert kd == k or (info["rank_deficient"] and kd >= 3)
+    assert np.max(np.abs(S[:3] - s[:3]) / s[:3]) < 1e-6
+    assert np.all(S[3:kd] < 1e-5 * s[0])
+    assert np.linalg.norm(V[:, :kd].T @ V[:, :kd] - np.eye(kd)) < 1e-10
+    assert np.all(np.isfinite(U))
+    for l in range(3):
+        assert line_angle(V[:, l], dk.V[:, l]) < 1e-4
+
+
 def test_nan_is_nonfinite(ctx):
     A = synth.gaussian_dense(100, 40, seed=1)
     A[17, 3] = np.nan
