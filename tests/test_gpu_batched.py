@@ -134,6 +134,35 @@ def test_batched_zero_problem_rank_deficient(ctx):
     assert np.max(np.abs(out[1][1].cpu().numpy() - dk.s[:2]) / dk.s[:2]) < 1e-6
 
 
+def test_batched_rank_below_k(ctx):
+    """In a batch: an exact rank-3 FP32 A (1,500 x 300, s = 3, 2, 1) asked for
+    k = 6 with fixed iterations, next to a wide rank-2 A (200 x 900, left
+    side) asked for k = 4.  The nonzero triplets meet the closed form, the
+    rest have sigma at rounding level, U and V stay finite and the iterate
+    side of each problem (V for the tall one, U for the wide one) stays
+    orthonormal to 1e-10 (or the problem stops rank-deficient after its
+    nonzero triplets)."""
+    specs = [(1500, 300, 6, [3.0, 2.0, 1.0], 5), (200, 900, 4, [2.0, 0.5], 6)]
+    probs, truth = [], []
+    for m, n, k, sv, seed in specs:
+        s = np.zeros(min(m, n))
+        s[:len(sv)] = sv
+        dk = synth.dense_known(m, n, s, seed=seed, dtype=np.float32)
+        st = synth.start_vectors(k, n if m >= n else m, seed=seed + 50)
+        probs.append(dict(A=to_dev(dk.A), k=k, eps=1e-8, v0=to_dev(st), fixed_iters=[200] * k, gram="bf16x3"))
+        truth.append((len(sv), s))
+    out = P.tsvd_dense_batched(ctx, probs, raise_errors=True)
+    for (U, S, V, info), (r, s), p in zip(out, truth, probs):
+        U, S, V = U.cpu().numpy(), S.cpu().numpy(), V.cpu().numpy()
+        k, kd = p["k"], info["k_done"]
+        assert kd == k or (info["rank_deficient"] and kd >= r)
+        assert np.max(np.abs(S[:r] - s[:r]) / s[:r]) < 1e-6
+        assert np.all(S[r:kd] < 1e-5 * s[0])
+        W = V if info["branch_right"] else U
+        assert np.linalg.norm(W[:, :kd].T @ W[:, :kd] - np.eye(kd)) < 1e-10
+        assert np.all(np.isfinite(U)) and np.all(np.isfinite(V))
+
+
 def test_batched_invalid_arguments_and_budget(ctx):
     dk, st = make_problem(300, 100, 2, "fp32", seed=3)
     good = dict(A=to_dev(dk.A), k=2, eps=1e-8, v0=to_dev(st))
