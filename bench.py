@@ -100,7 +100,7 @@ def source_hash(key: str) -> str:
 
 def measured_mfma():
     """Dense MFMA rates of this GPU from the C++ driver's peak loops (every CU,
-    four independent chains per wave), or None when the driver is not built."""
+    four independent chains per wave), or None when tsvd_bench is not built."""
     exe = os.path.join(ROOT, "paper_2208_08410_amd", "tsvd_bench")
     if not os.path.exists(exe):
         return None
@@ -627,7 +627,7 @@ def main():
     a = parse()
     if a.gpus != 1:
         print("bench.py: this build runs on one GPU; multi-GPU (N > 1) is not implemented "
-              "(the sharding design is described in DESIGN.md).", file=sys.stderr)
+              "(how the path would shard is part of the design notes).", file=sys.stderr)
         return 2
     if a.workload == "batch":
         return batch_main(a)
