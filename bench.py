@@ -626,7 +626,7 @@ def sparse_main(a):
 def main():
     a = parse()
     if a.gpus != 1:
-        print("bench.py: this build runs on one GPU; multi-GPU (N > 1) is not implemented "
+        print("bench.py: the library runs on one GPU; multi-GPU (N > 1) is not implemented "
               "(how the path would shard is part of the design notes).", file=sys.stderr)
         return 2
     if a.workload == "batch":

@@ -50,7 +50,7 @@ typedef enum {
   TSVD_ERR_NONFINITE = 4,      /* NaN/Inf met in the Gram, a product or a norm */
   TSVD_ERR_HIP = 5,            /* a HIP runtime call failed */
   TSVD_ERR_REJECTED = 6,       /* the server cannot admit the request even when idle */
-  TSVD_ERR_UNSUPPORTED = 7,    /* valid request outside what this build implements */
+  TSVD_ERR_UNSUPPORTED = 7,    /* valid request outside what the library implements */
   TSVD_ERR_INTERNAL = 8        /* an internal consistency check failed (e.g. a bounded device wait timed out) */
 } tsvd_status;
 
