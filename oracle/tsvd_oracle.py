@@ -16,11 +16,12 @@ Out-of-Memory SVD on CPU/GPU Architectures"):
 
 Four forms of the method are given, equal in exact arithmetic:
 
-``tsvd_literal``   Algorithm 1 + 2 exactly as printed: the residual X is formed
-                   explicitly for every triplet and its Gram re-formed.  Small
-                   inputs only.
+``tsvd_literal``   Deflation by the explicit residual (Algorithm 1): for every
+                   triplet the residual X = A - sum_j sigma_j u_j v_j^T is
+                   formed in full and the power method runs on its Gram.
+                   Memory O(m n) per triplet: small inputs only.
 ``tsvd_gram``      The Gram B0 = A^T A (or A A^T) is formed once (the paper's
-                   dense path reuses the Gram for every iteration, Sec. V-A)
+                   dense path reuses the Gram for every iteration, Sec. VI-A)
                    and each triplet runs the power method on P B0 P, with
                    P = I - V V^T applied as two projections.  Because
                    u_j sigma_j = A v_j (Algorithm 1), X_l = A P and
@@ -256,12 +257,16 @@ def _fixed_for(l: int, fixed_iters):
 
 def tsvd_literal(A: np.ndarray, eps: float, k: int = -1, starts: np.ndarray | None = None,
                  max_iter: int = 10000, fixed_iters=None, branch: str = "ge") -> TSVDResult:
-    """Algorithm 1 with Algorithm 2, as printed (explicit residual, Gram per l).
+    """Truncated SVD with deflation by the explicit residual (Algorithm 1).
 
-    For l = 1..k: X = A - U[:l] diag(sigma[:l]) V[:l]^T; if the right branch,
-    v = SVD_1D(X) on B = X^T X, u = A v, sigma = ||u||, u = u / sigma;
-    otherwise u = SVD_1D(X) on B = X X^T, v = A^T u, sigma = ||v||,
-    v = v / sigma.  Memory O(m n) per triplet: small inputs only.
+    Triplet l is the dominant singular triplet of the residual that remains
+    once the l - 1 rank-one terms already found are subtracted from A,
+    X_l = A - sum_{j<l} sigma_j u_j v_j^T.  Its right (or left) singular
+    vector is the dominant eigenvector of the Gram X_l^T X_l (or X_l X_l^T),
+    found by the power method (Algorithm 2); the other vector and sigma then
+    come from A itself (reading R4): u = A v / ||A v||, sigma = ||A v||, or
+    the mirror for the left branch.  Memory O(m n) per triplet: small inputs
+    only.
     """
     A = np.asarray(A, dtype=np.float64)
     m, n = A.shape

@@ -12,7 +12,7 @@ underlying bit generator is Philox (counter based), so any piece can be
 regenerated on its own.
 
 Workload recipes (shapes and distributions follow the paper's synthetic
-random inputs, Sec. V-A, and the five configurations this library is
+random inputs, Sec. VI-A, and the five configurations this library is
 measured on):
 
 * ``dense_known``: A = U diag(s) V^T with U (m x r) and V (n x r) orthonormal

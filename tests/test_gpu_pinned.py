@@ -35,17 +35,24 @@ def test_pinned_bitwise_equals_device(ctx, rpb, q, gram):
     assert np.array_equal(Up.cpu().numpy(), Ud.cpu().numpy())
 
 
-def test_pinned_default_batches_vs_oracle(ctx):
+@pytest.mark.parametrize("rpb,q", [(0, 2), (4000, 2), (2500, 3)])
+def test_pinned_batches_vs_oracle(ctx, rpb, q):
+    """Default batches (one batch here) and rows_per_block well below m, so
+    that 8 or 12 batches stream through 2 or 3 device buffers with a ragged
+    last batch: sigma, v and u against the FP64 oracle in trajectory mode."""
     m, n, k, eps = 30000, 256, 5, 1e-9
     dk = synth.dense_known(m, n, synth.spectrum_geometric(0.9, n), seed=4, dtype=np.float32)
     st = synth.start_vectors(k, n, seed=1)
     ref = O.tsvd_gram(dk.A, eps, k, st)
-    U, S, V, info = P.tsvd_dense(ctx, pinned(dk.A), k, eps, to_dev(st), fixed_iters=ref.iters)
-    S = S.cpu().numpy(); V = V.cpu().numpy()
+    U, S, V, info = P.tsvd_dense(ctx, pinned(dk.A), k, eps, to_dev(st), fixed_iters=ref.iters, rows_per_block=rpb,
+                                 queue_depth=q)
+    assert info["h2d_bytes"] == 2 * m * n * 4
+    S = S.cpu().numpy(); V = V.cpu().numpy(); U = U.cpu().numpy()
     assert np.max(np.abs(S - ref.S) / ref.S) < 1e-6
-    Vr = O.canonical(ref.U, ref.V)[1]
+    Ur, Vr = O.canonical(ref.U, ref.V)
     for l in range(k):
         assert line_angle(V[:, l], Vr[:, l]) < 1e-4
+        assert line_angle(U[:, l], Ur[:, l]) < 1e-4
 
 
 def test_pinned_rejects_pageable_and_left_branch(ctx):

@@ -165,6 +165,35 @@ def test_sparse_trajectory_vs_oracle(ctx, m, n):
     assert np.linalg.norm(Q.T @ Q - np.eye(k)) < 1e-10
 
 
+def test_sparse_trajectory_many_tiles_vs_oracle(ctx):
+    """The library's default tiling at a size where it spans many row chunks
+    (2^11-row chunks, 538 of them) and five column slices (2^18 columns each,
+    the last ragged): m = n = 1.1e6 with Poisson(50) uniform columns per row
+    (draw order, repeats kept), k = 4 triplets of 20 fixed iterations each,
+    against the implicit oracle on the same matrix (Eq. 2 in factored form,
+    Alg. 4's benchmark mode)."""
+    import torch
+    m = n = 1_100_000
+    k, iters = 4, 20
+    print(f"[sparse] CSR {m}x{n}, 50 nonzeros per row", flush=True)
+    rp, ci, va = synth.csr_uniform_torch(m, n, 50.0 / n, 13, torch.device("cuda:0"))
+    M = sp.csr_matrix((va.cpu().numpy().astype(np.float64), ci.cpu().numpy(), rp.cpu().numpy()), shape=(m, n))
+    c = P.tsvd_csr_create(ctx, rp, ci, va, (m, n))
+    st = synth.start_vectors(k, n, seed=8)
+    print("[sparse] oracle", flush=True)
+    ref = O.tsvd_implicit(lambda x: M @ x, lambda y: M.T @ y, (m, n), 0.0, k, st, max_iter=iters)
+    print("[sparse] GPU", flush=True)
+    U, S, V, info = P.tsvd_sparse(ctx, c, k, 0.0, to_dev(st), max_iter=iters)
+    assert info["iters"] == [iters] * k
+    S = S.cpu().numpy(); V = V.cpu().numpy(); U = U.cpu().numpy()
+    assert np.allclose(S, ref.S, rtol=1e-6)
+    Ur, Vr = O.canonical(ref.U, ref.V)
+    for l in range(k):
+        assert line_angle(V[:, l], Vr[:, l]) < 1e-4
+        assert line_angle(U[:, l], Ur[:, l]) < 1e-4
+    c.close()
+
+
 def test_sparse_matches_dense_route(ctx):
     """The dense (Gram) and sparse (implicit) routes give the same triplets for
     a sparse matrix small enough to densify (FP64 Gram, tight eps)."""
