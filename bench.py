@@ -110,6 +110,20 @@ def measured_mfma():
     return json.loads(r.stdout.strip().splitlines()[-1])
 
 
+def measured_exchange(d: int):
+    """Microseconds per exchange round of the power kernel's iteration
+    exchange alone (the C++ driver's probe: every workgroup publishes its rows
+    of a d-vector and two partial sums and gathers all of them, one workgroup
+    per CU), or None when tsvd_bench is not built."""
+    exe = os.path.join(ROOT, "paper_2208_08410_amd", "tsvd_bench")
+    if not os.path.exists(exe):
+        return None
+    r = subprocess.run([exe, "exchange", str(d), "4000"], capture_output=True, text=True, timeout=120)
+    if r.returncode != 0:
+        return None
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
 def measured_traffic(kernel: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary (FETCH_SIZE, WRITE_SIZE scaled by a reference copy), or None when
@@ -136,19 +150,19 @@ def measured_traffic(kernel: str):
     return None
 
 
-def power_bytes_per_launch(iters, k, n, elem=4):
-    """Algorithmic bytes of the power-iteration launch: every iteration reads B
-    (n^2 elements) once; every triplet but the last adds one more product with
-    B (w = B v) and a read + write of B for the deflation update."""
-    units = sum(iters) + 3 * (k - 1)
-    return units * n * n * elem, units
+def power_exchange_rounds(iters, k):
+    """Exchange rounds of one power launch: one per iteration, and per triplet
+    the re-orthogonalisation all-reduce and the gather of v, plus the gathers
+    of w and of v again for every deflation (all triplets but the last)."""
+    return int(sum(iters)) + 2 * k + 2 * (k - 1)
 
 
-def cpu_baseline(A_dev, s, k, eps, seed):
-    """The FP64 oracle, as it stands, on a bounded sample of the workload."""
+def cpu_baseline(A_dev, s, k, eps, v0):
+    """The FP64 oracle, as it stands, on the whole workload: one complete
+    t-SVD of the same FP32 matrix (read as FP64) with the same start vectors
+    (Gram once, k projected power loops, u = A v for every triplet)."""
     import numpy as np
     import oracle as O
-    import synth
 
     try:
         from threadpoolctl import threadpool_info
@@ -156,33 +170,23 @@ def cpu_baseline(A_dev, s, k, eps, seed):
     except Exception:
         cores = os.cpu_count() or 1
     m, n = A_dev.shape
-    ms = min(m, 12500)
-    ks = 2
-    A_s = A_dev[:ms].cpu().double().numpy()
-    st = synth.start_vectors(ks, n, seed=seed)
+    A_h = A_dev.cpu().double().numpy()
+    st = v0.cpu().numpy()
     t0 = time.perf_counter()
-    B0 = O.gram_rowblocks(A_s)
+    B0 = O.gram_rowblocks(A_h)
     t_gram = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    r = O.tsvd_gram(A_s, eps, ks, st, B0=B0)
-    t_rest = time.perf_counter() - t0
-    # the per-triplet finish (u = A v) scales with m; the power loop does not
-    t0 = time.perf_counter()
-    for _ in range(3):
-        A_s @ r.V[:, 0]
-    t_fin_per = (time.perf_counter() - t0) / 3
-    t_power_per = max(t_rest - ks * t_fin_per, 1e-9) / ks
-    est = t_gram * (m / ms) + k * t_power_per + k * t_fin_per * (m / ms)
+    r = O.tsvd_gram(A_h, eps, k, st, B0=B0)
+    t_all = time.perf_counter() - t0
+    rel = float(np.max(np.abs(r.S - s[:k]) / s[:k]))
     return {
-        "value": k / est,
+        "value": k / t_all,
         "unit": "triplets/s",
         "cores": int(cores),
         "kind": "oracle",
-        "sample": (f"FP64 NumPy oracle (Gram once + projected power method) on the first {ms} rows with "
-                   f"{ks} triplets: Gram {t_gram:.2f} s scaled by m/{ms}, power loop {t_power_per:.2f} s per "
-                   f"triplet ({int(np.mean(r.iters))} iterations) times k={k}, u = A v {t_fin_per*1e3:.1f} ms per "
-                   f"triplet scaled by m/{ms} times k; estimated {est:.1f} s per t-SVD"),
-    }
+        "sample": (f"the whole workload: one FP64 NumPy oracle t-SVD of the same {m}x{n} matrix, k={k}, eps={eps}, "
+                   f"same start vectors ({int(np.sum(r.iters))} power iterations); Gram {t_gram:.1f} s, total "
+                   f"{t_all:.1f} s; sigma within {rel:.1e} of the closed form"),
+    }, r
 
 
 def serve_cpu_baseline(shapes, ks, eps, seed):
@@ -682,7 +686,6 @@ def main():
     t_fin = float(np.mean([i["t_final_ms"] for i in infos]))
     a_bytes = a.m * a.n * 4
     a_stream = 2 * a_bytes / ((t_gram + t_fin) * 1e-3) / 1e9
-    pbytes, punits = power_bytes_per_launch(info["iters"], a.k, a.n)
     phases = {"gram": t_gram, "power": t_eig, "finish": t_fin}
     dominant = max(phases, key=phases.get)
     # the library's default tiles: 256 x 256 for BF16X3 Grams of dimension >= 1024, else 128 x 128
@@ -707,19 +710,31 @@ def main():
         "effective_fp32_equiv_tflops": gram_flops_alg / (t_gram * 1e-3) / 1e12,
     }
     traffic = measured_traffic("power_kernel<float,16,2>") if c2_shape else None
+    iters_total = int(sum(info["iters"]))
+    rounds = power_exchange_rounds(info["iters"], a.k)
+    ex = measured_exchange(a.n)
+    floor_ms = rounds * ex["exchange_us_per_round"] * 1e-3 if ex else None
+    gemv_flops = 2.0 * a.n * a.n * (iters_total + (a.k - 1))
     roof_power = {
-        "kernel": "power_kernel<float,16,2>",
-        "bound": "hbm",
-        "achieved": pbytes / (t_eig * 1e-3) / 1e9,
-        "peak": HBM_PEAK_GBS,
-        "unit": "GB/s",
-        "frac": pbytes / (t_eig * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "kernel": "power_kernel<float,16,2>" if a.n == 4096 else "power_kernel<float,...>",
+        "bound": "exchange latency",
+        "achieved": rounds / (t_eig * 1e-3),
+        "peak": (rounds / (floor_ms * 1e-3)) if floor_ms else None,
+        "unit": "exchange rounds/s",
+        "frac": (floor_ms / t_eig) if floor_ms else None,
         "traffic": traffic,
         "traffic_note": "HBM bytes per launch from profiles/traffic_*.txt (rocprofv3 FETCH_SIZE/WRITE_SIZE, scaled "
-                        "by a reference copy); far below the algorithmic bytes because B stays on chip",
-        "units_per_launch": punits,
-        "bytes_per_unit": a.n * a.n * 4,
-        "us_per_iteration": t_eig * 1e3 / max(1, sum(info["iters"])),
+                        "by a reference copy); B stays on chip, so HBM traffic is far below n^2 * 4 B per iteration",
+        "exchange_rounds_per_launch": rounds,
+        "exchange_floor_us_per_round": ex["exchange_us_per_round"] if ex else None,
+        "exchange_floor_ms_per_launch": floor_ms,
+        "us_per_iteration": t_eig * 1e3 / max(1, iters_total),
+        "note": "the kernel's bound: every iteration ends in an all-gather of the iterate among all workgroups; "
+                "peak = rounds per launch at the measured latency of that exchange alone (tsvd_bench exchange)",
+        "alu_view": {"bound": "alu", "achieved": gemv_flops / (t_eig * 1e-3) / 1e12, "peak": FP32_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": gemv_flops / (t_eig * 1e-3) / 1e12 / FP32_PEAK_TFLOPS,
+                     "note": "2 n^2 flops per product (one per iteration, one per deflation) against the FP32 "
+                             "vector peak"},
     }
     roofline = roof_power if dominant == "power" else roof_gram
     out = {
@@ -777,7 +792,28 @@ def main():
         if a.gram == "bf16x3":
             roof_gram["frac_of_measured_peak"] = roof_gram["achieved"] / mm["mfma_bf16_tflops"]
     if a.cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(A, s, a.k, a.eps, a.seed)
+        progress("timing the FP64 oracle on the whole workload")
+        out["cpu_baseline"], ref = cpu_baseline(A, s, a.k, a.eps, v0)
+        # parity with the oracle on this workload: the GPU path in trajectory
+        # mode (the oracle's iteration counts, same start vectors), both Gram forms
+        import oracle as O
+        Ur, Vr = O.canonical(ref.U, ref.V)
+        par = {}
+        for g in ([a.gram, "fp32"] if a.gram != "fp32" else ["fp32"]):
+            Ut, St, Vt_, it_ = P.tsvd_dense(ctx, A, a.k, a.eps, v0, gram=g, fixed_iters=[int(x) for x in ref.iters])
+            St, Ut, Vt_ = St.cpu().numpy(), Ut.cpu().numpy(), Vt_.cpu().numpy()
+            cv = np.clip(np.abs(np.sum(Vt_ * Vr, axis=0)), 0, 1)
+            cu = np.clip(np.abs(np.sum(Ut * Ur, axis=0)), 0, 1)
+            sv_ = np.sqrt(np.maximum(0.0, 1 - cv * cv))
+            su_ = np.sqrt(np.maximum(0.0, 1 - cu * cu))
+            par[g] = {"sigma_rel_vs_oracle": float(np.max(np.abs(St - ref.S) / ref.S)),
+                      "v_angle_vs_oracle_rad": float(np.max(np.arctan2(sv_, cv))),
+                      "u_angle_vs_oracle_rad": float(np.max(np.arctan2(su_, cu)))}
+            par[g]["meets_1e-6_sigma_1e-4_rad"] = bool(par[g]["sigma_rel_vs_oracle"] < 1e-6 and
+                                                       par[g]["v_angle_vs_oracle_rad"] < 1e-4 and
+                                                       par[g]["u_angle_vs_oracle_rad"] < 1e-4)
+        out["parity_vs_oracle"] = par
+        out["meets_1e-6"] = bool(out["meets_1e-6"] and par[a.gram]["meets_1e-6_sigma_1e-4_rad"])
     ctx.close()
     print(json.dumps(out), flush=True)
     return 0

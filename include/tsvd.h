@@ -216,7 +216,7 @@ typedef struct {
 
 /* Algorithm 1 for `count` independent problems of any mix of shapes, in three
  * grouped launches: the Gram of every problem (work units = problem x split-K
- * chunk x triangle tile, Algorithm 3's block products), one cooperative power
+ * chunk x triangle tile, Algorithm 3's block products), one persistent power
  * launch in which workgroups form a team per problem as they come free (the
  * problems wait in a queue, longest first; a team runs Algorithm 2 with
  * deflation on its problem, then its members return to the queue), and the

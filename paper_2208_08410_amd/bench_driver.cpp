@@ -11,6 +11,11 @@
 //   tsvd_bench mfma
 //     dense MFMA peak loops on every CU (BF16 32x32x16 and FP64 16x16x4, four
 //     independent accumulators per wave): the measured roofline denominators
+//   tsvd_bench exchange [d] [rounds]
+//     the power kernel's per-iteration exchange alone (csrc/exchange.h: every
+//     workgroup publishes its rows of a d-vector and two partial sums, then
+//     gathers all of them), one workgroup per CU, no products: the latency
+//     floor of one power iteration
 //   tsvd_bench batch COUNT [steps warmup seed team_kib]
 //     COUNT problems of the serving mix (m log-uniform in [1024, 65536], n in
 //     [128, 4096], k in {8, 16, 32, 64}, s_i = 0.95^i, eps = 5e-8) solved by
@@ -30,6 +35,7 @@
 #include <vector>
 
 #include "../include/tsvd.h"
+#include "csrc/exchange.h"
 
 static uint64_t splitmix(uint64_t x) {
   x += 0x9E3779B97F4A7C15ull;
@@ -115,6 +121,94 @@ static int run_mfma() {
          f64_flops / (best_f64 * 1e-3) / 1e12, num_cu);
   fflush(stdout);
   hipFree(out);
+  return 0;
+}
+
+// `rounds` iterations of the power kernel's exchange with nothing else: each
+// workgroup owns ceil(d / G) entries, publishes them with its two partial
+// sums, gathers the whole vector and every partial, and derives its next
+// entries from what it gathered.  The dynamic LDS request matches the power
+// kernel's (the CU's whole LDS) so that placement is one workgroup per CU.
+__global__ __launch_bounds__(256, 1) void exchange_probe_kernel(uint64_t* xex, uint64_t* pex, int d, int rounds,
+                                                                int64_t spin, int* err) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int G = gridDim.x, b = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int dpad = (d + 3) & ~3;
+  const int rpb = (d + G - 1) / G;
+  const int r0 = b * rpb;
+  const int nrows = max(0, min(rpb, d - r0));
+  double* yv = (double*)smem;
+  double* red = yv + ((rpb + 1) & ~1);
+  int* flag = (int*)(red + 8);
+  float* xs = (float*)(red + 10);
+  for (int i = tid; i < nrows; i += 256) yv[i] = 1.0 + (r0 + i) * 1e-3;
+  __syncthreads();
+  for (int r = 1; r <= rounds; r++) {
+    uint64_t* xb = xex + (int64_t)(r & 1) * dpad;
+    uint64_t* pb = pex + (int64_t)(r & 1) * G * 4;
+    tsvd::publish_rows<float>(xb, (uint32_t)r, r0, nrows, yv);
+    if (wave == 3) {
+      double q = 0.0, dd = 0.0;
+      for (int i = lane; i < nrows; i += 64) { q = fma(yv[i], yv[i], q); dd += yv[i]; }
+      q = tsvd::wave_sum(q);
+      dd = tsvd::wave_sum(dd);
+      if (lane < 4) tsvd::ll_store(pb + 4 * (int64_t)b + lane, (uint32_t)r, tsvd::f64_half(lane < 2 ? q : dd, lane & 1));
+    }
+    double q, dd;
+    if (!tsvd::gather_iteration<float, 16>(xb, pb, (uint32_t)r, d, b, G, xs, red, flag, spin, q, dd)) {
+      if (tid == 0) atomicMax(err, 1);
+      return;
+    }
+    for (int i = tid; i < nrows; i += 256) yv[i] = (double)xs[r0 + i] / (1.0 + 1e-9 * q);
+    __syncthreads();
+  }
+}
+
+static int run_exchange(int d, int rounds) {
+  int num_cu = 0, max_lds = 0;
+  if (hipDeviceGetAttribute(&num_cu, hipDeviceAttributeMultiprocessorCount, 0) != hipSuccess ||
+      hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, 0) != hipSuccess)
+    return 1;
+  if (d < 4 * num_cu || d > 16384 || rounds < 1) { fprintf(stderr, "exchange: need 4 * CUs <= d <= 16384\n"); return 2; }
+  const int G = num_cu;
+  const int dpad = (d + 3) & ~3;
+  const size_t need = (size_t)(((d + G - 1) / G + 1) / 2 * 2 + 10) * 8 + (size_t)dpad * 4;
+  size_t lds = (size_t)max_lds;
+  if (lds > 160 * 1024) lds = 160 * 1024;
+  if (need > lds) { fprintf(stderr, "exchange: LDS\n"); return 2; }
+  const void* fn = (const void*)exchange_probe_kernel;
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) return 1;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, lds) != hipSuccess || per_cu < 1) return 1;
+  uint64_t *xex, *pex;
+  int* err;
+  const size_t xw = (size_t)2 * dpad, pw = (size_t)2 * G * 4;
+  if (hipMalloc(&xex, xw * 8) || hipMalloc(&pex, pw * 8) || hipMalloc(&err, 4)) return 1;
+  hipEvent_t e0, e1;
+  hipEventCreate(&e0); hipEventCreate(&e1);
+  int64_t spin = (int64_t)1 << 21;
+  float best = 1e30f;
+  for (int rep = 0; rep < 4; rep++) {
+    const int R = rep == 0 ? 100 : rounds;  // the first launch warms up
+    hipMemset(xex, 0, xw * 8);
+    hipMemset(pex, 0, pw * 8);
+    hipMemset(err, 0, 4);
+    void* args[] = {(void*)&xex, (void*)&pex, (void*)&d, (void*)&R, (void*)&spin, (void*)&err};
+    hipEventRecord(e0, nullptr);
+    if (hipLaunchKernel(fn, dim3(G), dim3(256), args, lds, nullptr) != hipSuccess) return 1;
+    hipEventRecord(e1, nullptr);
+    hipEventSynchronize(e1);
+    int herr = 0;
+    hipMemcpy(&herr, err, 4, hipMemcpyDeviceToHost);
+    if (herr) { fprintf(stderr, "exchange: a bounded wait timed out\n"); return 1; }
+    float t;
+    hipEventElapsedTime(&t, e0, e1);
+    if (rep > 0 && t < best) best = t;
+  }
+  printf("{\"exchange_us_per_round\": %.3f, \"d\": %d, \"workgroups\": %d, \"rounds\": %d}\n",
+         best * 1e3 / rounds, d, G, rounds);
+  fflush(stdout);
+  hipFree(xex); hipFree(pex); hipFree(err);
   return 0;
 }
 
@@ -273,6 +367,8 @@ static int run_batch(int count, int steps, int warmup, uint64_t seed, int team_k
 
 int main(int argc, char** argv) {
   if (argc > 1 && argv[1][0] == 'm') return run_mfma();
+  if (argc > 1 && argv[1][0] == 'e')
+    return run_exchange(argc > 2 ? atoi(argv[2]) : 4096, argc > 3 ? atoi(argv[3]) : 4000);
   if (argc > 1 && argv[1][0] == 'b')
     return run_batch(argc > 2 ? atoi(argv[2]) : 64, argc > 3 ? atoi(argv[3]) : 3, argc > 4 ? atoi(argv[4]) : 1,
                      argc > 5 ? strtoull(argv[5], nullptr, 10) : 7, argc > 6 ? atoi(argv[6]) : 0);

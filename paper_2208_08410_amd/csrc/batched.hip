@@ -6,7 +6,7 @@
 //   Gram:   one launch per (Gram mode, side) whose workgroups are the
 //           (problem, split-K chunk, 128x128 triangle tile) units of every
 //           problem, then one deterministic reduction launch.
-//   Power:  one cooperative launch; workgroups form a team for each problem
+//   Power:  one persistent launch; workgroups form a team for each problem
 //           as they come free (problems queued longest first) and the team
 //           runs the single-problem body on it (a team is to one problem what
 //           the whole grid is to a single call).

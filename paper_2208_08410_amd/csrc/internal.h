@@ -74,7 +74,7 @@ int power_plan(int dtype_bytes, int d, int k, int num_cu, size_t max_lds, int ma
 int power_launch(int is_f64, const PowerPlan& p, PowerArgs a, hipStream_t stream);
 // batched launch (FP32 Grams), teams formed on the fly: problems order[0..n)
 // (queue order) with team sizes gsize[h]; sched holds 1 + n ints, zero on
-// entry; grid workgroups, one per CU (cooperative); zero_words of exchange
+// entry; grid workgroups, one per CU (all resident at once); zero_words of exchange
 // memory at zero_base are cleared first
 // static LDS of the batched power kernel (its dynamic LDS must leave room for it)
 size_t power_dyn_static_lds();

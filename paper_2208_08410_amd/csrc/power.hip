@@ -1,5 +1,5 @@
 // Power iteration with deflation on a symmetric Gram matrix (Algorithm 2, run
-// once per triplet as Algorithm 1 does), as ONE persistent cooperative launch.
+// once per triplet as Algorithm 1 does), as ONE persistent launch.
 //
 // Layout: workgroup b owns the contiguous rows R_b of B (rpb rows).  The first
 // cache_rows of them are kept in LDS for the whole launch; the rest are read
@@ -30,6 +30,7 @@
 #include <type_traits>
 
 #include "common.h"
+#include "exchange.h"
 #include "internal.h"
 
 namespace tsvd {
@@ -250,94 +251,6 @@ __device__ __forceinline__ bool allreduce_blocks(uint64_t* pbuf, int pw, int b, 
     }
     __syncthreads();
   }
-  const bool res = *flag != 0;
-  __syncthreads();
-  return res;
-}
-
-// Publish own rows r0 + i (i < nrows) of a vector in B's type: one word per
-// FP32 element, two (low, high half) per FP64 element, each thread storing
-// one word so that a wave's words leave in one store instruction.
-template <typename BT>
-__device__ __forceinline__ void publish_rows(uint64_t* buf, uint32_t ep, int r0, int nrows, const double* v) {
-  if constexpr (sizeof(BT) == 4) {
-    for (int i = threadIdx.x; i < nrows; i += 256) ll_store(buf + r0 + i, ep, __float_as_uint((float)v[i]));
-  } else {
-    for (int w = threadIdx.x; w < 2 * nrows; w += 256) ll_store(buf + 2 * (int64_t)r0 + w, ep, f64_half(v[w >> 1], w & 1));
-  }
-}
-
-// Iteration exchange: wait until every y word of this epoch (rotated start per
-// block to spread the requests over memory channels) and every block's two
-// partials are published; y lands in xs (raw), partials are summed with a
-// fixed-shape tree.  With G = 0 only the vector is gathered (q = dd = 0).
-// Returns false (block-uniform) on a timed-out wait.
-// W words per thread per round: 16 puts up to 4096 words in flight at once
-// (one round for a 4096-entry FP32 iterate), 8 keeps registers for smaller d.
-template <typename BT, int W>
-__device__ __forceinline__ bool gather_iteration(const uint64_t* xb, const uint64_t* pb, uint32_t ex, int d, int b, int G, BT* xs,
-                                 double* red, int* flag, int64_t spin_limit, double& q, double& dd) {
-  constexpr int WPE = sizeof(BT) / 4;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int count = d * WPE;
-  const int rot = (int)(((int64_t)b * 1031) % count);
-  uint32_t* raw = (uint32_t*)xs;
-  int64_t budget = spin_limit;
-  bool ok = true;
-  double pq = 0.0, pd = 0.0;
-  for (int base = 0; base < count && ok; base += 256 * W) {
-    uint64_t w[W];
-    uint64_t pw4[4];
-    const bool first = base == 0;
-#pragma unroll
-    for (int j = 0; j < W; j++) {
-      const int i = base + tid + 256 * j;
-      int ii = i + rot;
-      if (ii >= count) ii -= count;
-      w[j] = i < count ? ll_load(xb + ii) : ((uint64_t)ex << 32);
-    }
-#pragma unroll
-    for (int j = 0; j < 4; j++) pw4[j] = (first && tid < G) ? ll_load(pb + 4 * (int64_t)tid + j) : ((uint64_t)ex << 32);
-    while (true) {
-      bool all = true;
-#pragma unroll
-      for (int j = 0; j < W; j++) all = all && ((uint32_t)(w[j] >> 32) == ex);
-#pragma unroll
-      for (int j = 0; j < 4; j++) all = all && ((uint32_t)(pw4[j] >> 32) == ex);
-      if (all) break;
-      if (--budget <= 0) { ok = false; break; }
-      __builtin_amdgcn_s_sleep(1);
-#pragma unroll
-      for (int j = 0; j < W; j++) {
-        const int i = base + tid + 256 * j;
-        int ii = i + rot;
-        if (ii >= count) ii -= count;
-        if (i < count && (uint32_t)(w[j] >> 32) != ex) w[j] = ll_load(xb + ii);
-      }
-#pragma unroll
-      for (int j = 0; j < 4; j++)
-        if (first && tid < G && (uint32_t)(pw4[j] >> 32) != ex) pw4[j] = ll_load(pb + 4 * (int64_t)tid + j);
-    }
-    if (ok) {
-#pragma unroll
-      for (int j = 0; j < W; j++) {
-        const int i = base + tid + 256 * j;
-        int ii = i + rot;
-        if (ii >= count) ii -= count;
-        if (i < count) raw[ii] = (uint32_t)w[j];
-      }
-      if (first && tid < G) { pq = ll_join_f64(pw4[0], pw4[1]); pd = ll_join_f64(pw4[2], pw4[3]); }
-    }
-  }
-  if (tid == 0) *flag = 1;
-  __syncthreads();
-  if (!ok) *flag = 0;
-  pq = wave_sum(pq);
-  pd = wave_sum(pd);
-  if (lane == 0) { red[wave] = pq; red[4 + wave] = pd; }
-  __syncthreads();
-  q = (red[0] + red[1]) + (red[2] + red[3]);
-  dd = (red[4] + red[5]) + (red[6] + red[7]);
   const bool res = *flag != 0;
   __syncthreads();
   return res;
@@ -815,6 +728,22 @@ int power_plan(int dtype_bytes, int d, int k, int num_cu, size_t max_lds, int ma
   return 0;
 }
 
+// compute units of the current device (cached per device)
+static int max_cus() {
+  static int cus[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) { (void)hipGetLastError(); return 1 << 20; }
+  if (cus[dev] == 0) {
+    int c = 0;
+    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0) {
+      (void)hipGetLastError();
+      return 1 << 20;
+    }
+    cus[dev] = c;
+  }
+  return cus[dev];
+}
+
 __global__ void zero_words_kernel(uint64_t* p, size_t n) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0;
 }
@@ -845,7 +774,12 @@ int power_launch(int is_f64, const PowerPlan& p, PowerArgs a, hipStream_t stream
   int per_cu = 0;
   TSVD_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, p.lds_bytes));
   if (per_cu < 1) return -2;
-  TSVD_HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(p.G), dim3(256), args, p.lds_bytes, stream));
+  // An ordinary launch: G <= CUs x per_cu, so every workgroup is resident at
+  // once on an otherwise idle device (the kernel's waits are bounded: a member
+  // that cannot start in time makes the call fail, never hang).  The runtime's
+  // cooperative-launch path is not used; it added nothing but a launch check.
+  if ((int64_t)p.G > (int64_t)per_cu * max_cus()) return -2;
+  TSVD_HIP_TRY(hipLaunchKernel(fn, dim3(p.G), dim3(256), args, p.lds_bytes, stream));
   return 0;
 }
 
@@ -873,7 +807,8 @@ int power_dyn_launch(const PowerArgs* d_probs, const int* d_order, const int* d_
   if (per_cu < 1) return -2;
   int64_t join_spin = (int64_t)1 << 30;
   void* args[] = {(void*)&d_probs, (void*)&d_order, (void*)&d_gsize, (void*)&nprob, (void*)&d_sched, (void*)&join_spin};
-  TSVD_HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(grid), dim3(256), args, lds_bytes, stream));
+  if ((int64_t)grid > (int64_t)per_cu * max_cus()) return -2;
+  TSVD_HIP_TRY(hipLaunchKernel(fn, dim3(grid), dim3(256), args, lds_bytes, stream));
   return 0;
 }
 
