@@ -181,6 +181,20 @@ tsvd_status tsvd_finish_dense(tsvd_ctx* ctx, const void* A, int32_t dtype, int64
                               int32_t side, const double* X, int64_t ldx, int32_t k, double* W, int64_t ldw,
                               double* S, void* stream);
 
+/* The finishing pass of tsvd_finish_dense with no device allocation, for
+ * callers that cannot allocate (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same arguments and results, bit for
+ * bit (the same kernels run); the scratch that tsvd_finish_dense takes from the
+ * context's workspace ((ceil(M / 128) + 2) x k doubles, M = m for RIGHT, n for
+ * LEFT) lives instead in a fixed device array of 2^20 doubles (8 MiB) that each
+ * device holds for the life of the process.  Larger requests return
+ * UNSUPPORTED with a message.  Every call on one device shares that array:
+ * calls that overlap on one device (other streams, other contexts, other host
+ * threads) race and must be serialised by the caller.  Asynchronous. */
+tsvd_status tsvd_finish_dense_noalloc(tsvd_ctx* ctx, const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
+                                      int32_t side, const double* X, int64_t ldx, int32_t k, double* W, int64_t ldw,
+                                      double* S, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Whole t-SVD (Algorithm 1), dense A
  * ------------------------------------------------------------------------- */

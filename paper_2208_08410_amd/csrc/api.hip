@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -150,6 +151,43 @@ void tsvd_opts_default(tsvd_opts* o) {
   o->queue_depth = 2;
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free finishing pass: its scratch (column sums per row tile and
+// the scale/sign factors) lives in one file-scope device array instead of the
+// context's workspace.  Each device holds its own copy of the array; host
+// code reaches it only through the address hipGetSymbolAddress returns for
+// that device (kept in g_scratch_ptr), never through the array's name.
+// ---------------------------------------------------------------------------
+static constexpr int64_t kNoallocScratchDoubles = (int64_t)1 << 20;  // 8 MiB per device
+static __device__ __align__(256) double scratch[kNoallocScratchDoubles];
+static constexpr int kMaxDevices = 64;
+static double* g_scratch_ptr[kMaxDevices] = {};
+static std::mutex g_scratch_mu;
+
+// called with `device` current (tsvd_ctx_create); once per device
+static tsvd_status noalloc_scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return TSVD_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (g_scratch_ptr[device]) return TSVD_OK;
+  void* p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+    (void)hipGetLastError();
+    return TSVD_ERR_HIP;
+  }
+  g_scratch_ptr[device] = (double*)p;
+  return TSVD_OK;
+}
+
+static double* noalloc_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
+
+extern "C" {
+
 tsvd_status tsvd_ctx_create(int device, tsvd_ctx** out) {
   if (!out) return TSVD_ERR_INVALID_ARG;
   *out = nullptr;
@@ -175,6 +213,10 @@ tsvd_status tsvd_ctx_create(int device, tsvd_ctx** out) {
   }
   if (hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking) != hipSuccess) {
     delete c;
+    return TSVD_ERR_HIP;
+  }
+  if (device < kMaxDevices && noalloc_scratch_init(device) != TSVD_OK) {
+    tsvd_ctx_destroy(c);
     return TSVD_ERR_HIP;
   }
   *out = c;
@@ -333,6 +375,32 @@ tsvd_status tsvd_finish_dense(tsvd_ctx* ctx, const void* A, int32_t dtype, int64
   rc = finish_scale_sign_launch(W, ldw, M, S, nullptr, 0, 0, nullptr, 0, 0, k, 0,
                                 (double*)ctx->ws + finish_tiles(m, n, side) * k, (hipStream_t)stream);
   return from_internal(ctx, rc, "finish scale");
+}
+
+tsvd_status tsvd_finish_dense_noalloc(tsvd_ctx* ctx, const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
+                                      int32_t side, const double* X, int64_t ldx, int32_t k, double* W, int64_t ldw,
+                                      double* S, void* stream) {
+  if (!ctx) return TSVD_ERR_INVALID_ARG;
+  if (!A || !X || !W || !S) return fail(ctx, TSVD_ERR_INVALID_ARG, "null pointer");
+  if (m < 1 || n < 1 || lda < n) return fail(ctx, TSVD_ERR_INVALID_ARG, "bad shape");
+  if (dtype != TSVD_F32 && dtype != TSVD_F64) return fail(ctx, TSVD_ERR_INVALID_ARG, "bad dtype");
+  if (side != TSVD_SIDE_RIGHT && side != TSVD_SIDE_LEFT) return fail(ctx, TSVD_ERR_INVALID_ARG, "bad side");
+  const int64_t K = side == TSVD_SIDE_RIGHT ? n : m, M = side == TSVD_SIDE_RIGHT ? m : n;
+  if (k < 1 || k > (m < n ? m : n) || ldx < K || ldw < M) return fail(ctx, TSVD_ERR_INVALID_ARG, "bad k/ld");
+  const int64_t need = finish_workspace_doubles(m, n, side, k);
+  if (need > kNoallocScratchDoubles)
+    return fail(ctx, TSVD_ERR_UNSUPPORTED,
+                "allocation-free finish needs %lld doubles of scratch ((ceil(%lld / 128) + 2) x k); its device array "
+                "holds %lld",
+                (long long)need, (long long)M, (long long)kNoallocScratchDoubles);
+  double* ws = noalloc_scratch(ctx->device);
+  if (!ws) return fail(ctx, TSVD_ERR_HIP, "allocation-free scratch has no address on device %d", ctx->device);
+  hipSetDevice(ctx->device);
+  int rc = finish_launch(dtype == TSVD_F64, side, A, m, n, lda, X, ldx, k, W, ldw, S, ws, (hipStream_t)stream);
+  if (rc) return from_internal(ctx, rc, "finish (allocation-free)");
+  rc = finish_scale_sign_launch(W, ldw, M, S, nullptr, 0, 0, nullptr, 0, 0, k, 0, ws + finish_tiles(m, n, side) * k,
+                                (hipStream_t)stream);
+  return from_internal(ctx, rc, "finish scale (allocation-free)");
 }
 
 // Dense t-SVD of an FP32 A held in pinned host memory (Algorithm 3's
