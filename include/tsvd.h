@@ -85,8 +85,31 @@ typedef struct {
                               (pinned host); 0 = library default */
   int64_t hbm_budget;      /* device bytes the call may allocate for workspace; 0 = no limit */
   int32_t branch;          /* 0: m >= n iterates on v (A^T A); 1: m > n as printed in Algorithm 1 */
-  int32_t queue_depth;     /* device buffers in the host->device batch pipeline (>= 2; default 2) */
+  int32_t queue_depth;     /* device buffers in the host->device batch pipelines, 1..16 (default 2; the
+                              pinned-A Gram pipeline takes at least 2): A's row batches, sparse tile
+                              batches, and the factor batches below */
+  int32_t method;          /* dense A only (tsvd_method): how Algorithm 2's product is applied */
+  int32_t factor_loc;      /* implicit paths (sparse A, method IMPLICIT): where the iterated factor X lives
+                              (V on the right branch, U on the left): TSVD_LOC_DEVICE (default), or
+                              TSVD_LOC_PINNED_HOST: the caller's V (or U) output is pinned host memory, and
+                              every projection against the found vectors streams X to the device in
+                              factor_batches row batches through queue_depth device buffers (the paper's
+                              out-of-memory handling of the heavy co-factor, Sec. V-C) */
+  int32_t factor_batches;  /* n_b for factor_loc = PINNED_HOST: X's rows are cut into this many batches,
+                              each rounded up to a multiple of 4096 rows (so fewer may result); 0 = 1 */
 } tsvd_opts;
+
+/* How a dense t-SVD applies Algorithm 2's operator.
+ * GRAM:     form B = A^T A (or A A^T) once (Algorithm 3) and iterate on it; the
+ *           power iteration runs on chip when the iterate fits the on-chip
+ *           kernel, else as a host-driven loop of HBM-streamed B x products.
+ * IMPLICIT: never form B: every iteration applies A^T (A x) (or A (A^T x)) as
+ *           two mat-vecs over A (Equation 2 evaluated right to left); A in
+ *           pinned host memory is then streamed once per iteration (m >= n).
+ * AUTO:     GRAM when its workspace (B, split-K partials, finish sums, plus the
+ *           row-batch buffers for pinned A) fits hbm_budget and the device's
+ *           free memory, else IMPLICIT.                                       */
+typedef enum { TSVD_METHOD_AUTO = 0, TSVD_METHOD_GRAM = 1, TSVD_METHOD_IMPLICIT = 2 } tsvd_method;
 
 typedef struct {
   int32_t k_done;          /* triplets computed before a zero product stopped the run */
@@ -136,7 +159,9 @@ typedef struct {
                               after the call */
   int32_t sparse_col_bits; /* sparse products: column slices of 2^bits (0 = 2^18: 1 MiB of FP32 x);
                               row + column bits <= 32 */
-  int32_t reserved;
+  int32_t power_path;    /* Gram power iteration: 0 = the on-chip persistent kernel when the iterate fits
+                            it, else the host-driven loop of HBM-streamed B x products; 1 = always that
+                            loop (B is then left undeflated: deflation is a projection per iteration) */
 } tsvd_tuning;
 
 /* Set / read the context's tuning.  INVALID_ARG for out-of-range values. */

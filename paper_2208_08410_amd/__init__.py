@@ -56,6 +56,7 @@ OK, INVALID_ARG, OUT_OF_MEMORY, NOT_CONVERGED, NONFINITE, HIP, REJECTED, UNSUPPO
 F32, F64 = 0, 1
 LOC_DEVICE, LOC_PINNED_HOST = 0, 1
 GRAM = {"auto": 0, "fp32": 1, "bf16x3": 2, "fp64": 3}
+METHOD = {"auto": 0, "gram": 1, "implicit": 2}
 SIDE = {"right": 0, "left": 1}
 
 
@@ -78,6 +79,9 @@ class TsvdOpts(ctypes.Structure):
         ("hbm_budget", ctypes.c_int64),
         ("branch", ctypes.c_int32),
         ("queue_depth", ctypes.c_int32),
+        ("method", ctypes.c_int32),
+        ("factor_loc", ctypes.c_int32),
+        ("factor_batches", ctypes.c_int32),
     ]
 
 
@@ -90,7 +94,7 @@ class TsvdTuning(ctypes.Structure):
         ("group_kchunk", ctypes.c_int32),
         ("sparse_row_bits", ctypes.c_int32),
         ("sparse_col_bits", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("power_path", ctypes.c_int32),
     ]
 
 
@@ -275,16 +279,17 @@ class Context:
 
 
 TUNING_FIELDS = ("gram_tile", "gram_chunks", "power_blocks", "team_kib", "group_kchunk", "sparse_row_bits",
-                 "sparse_col_bits")
+                 "sparse_col_bits", "power_path")
 
 
 def set_tuning(ctx: Context, gram_tile: int = 0, gram_chunks: int = 0, power_blocks: int = 0, team_kib: int = 0,
-               group_kchunk: int = 0, sparse_row_bits: int = 0, sparse_col_bits: int = 0):
+               group_kchunk: int = 0, sparse_row_bits: int = 0, sparse_col_bits: int = 0, power_path: int = 0):
     """Set the context's launch-shape tuning (0 = library choice)."""
     t = TsvdTuning()
     t.gram_tile, t.gram_chunks, t.power_blocks = int(gram_tile), int(gram_chunks), int(power_blocks)
     t.team_kib, t.group_kchunk = int(team_kib), int(group_kchunk)
     t.sparse_row_bits, t.sparse_col_bits = int(sparse_row_bits), int(sparse_col_bits)
+    t.power_path = int(power_path)
     ctx.check(ctx.lib.tsvd_ctx_set_tuning(ctx.handle, ctypes.byref(t)))
 
 
@@ -423,12 +428,27 @@ def tsvd_finish_dense(ctx: Context, A, side, X, k, stream=None):
     return W, S
 
 
+def _factor_out(rows: int, k: int, device, factor: str):
+    """Output for the iterated factor: on the device, or pinned host memory
+    (factor="host")."""
+    torch = _torch()
+    if factor == "device":
+        return _colmajor_out(rows, k, device)
+    if factor == "host":
+        return torch.zeros((k, rows), dtype=torch.float64, pin_memory=True).T
+    raise ValueError('factor must be "device" or "host"')
+
+
 def tsvd_dense(ctx: Context, A, k, eps, v0, max_iter=10000, fixed_iters=None, gram="auto", rows_per_block=0,
-               hbm_budget=0, branch=0, stream=None, raise_not_converged=False, queue_depth=2):
+               hbm_budget=0, branch=0, stream=None, raise_not_converged=False, queue_depth=2, method="auto",
+               factor="device", factor_batches=1):
     """Whole t-SVD of a dense A.  A is a device tensor (resident in HBM) or a
-    pinned host tensor (``A.is_pinned()``: streamed in row batches).  Returns
-    (U, S, V, info) on the context's device, with U (m x k) and V (n x k)
-    column-major float64 and S float64."""
+    pinned host tensor (``A.is_pinned()``: streamed in row batches).  method:
+    "gram" (form the Gram once), "implicit" (A^T (A x) every iteration) or
+    "auto".  factor="host" keeps the iterated factor (V on the right branch,
+    U on the left) in pinned host memory, batched to the device in
+    factor_batches row batches for every projection.  Returns (U, S, V, info),
+    with U (m x k) and V (n x k) column-major float64 and S float64."""
     torch = _torch()
     m, n, lda = _rowmajor(A)
     kk = min(m, n) if k == -1 else k
@@ -441,11 +461,14 @@ def tsvd_dense(ctx: Context, A, k, eps, v0, max_iter=10000, fixed_iters=None, gr
     else:
         raise ValueError("A must be a device tensor or a pinned host tensor")
     _check_v0(v0, kk, d, dev)
-    U = _colmajor_out(m, kk, dev)
-    V = _colmajor_out(n, kk, dev)
+    U = _factor_out(m, kk, dev, factor if not right else "device")
+    V = _factor_out(n, kk, dev, factor if right else "device")
     S = torch.zeros(kk, dtype=torch.float64, device=dev)
     o, keep = _make_opts(ctx.lib, k, eps, v0, max_iter, fixed_iters, gram, rows_per_block, hbm_budget, branch)
     o.queue_depth = int(queue_depth)
+    o.method = METHOD[method] if isinstance(method, str) else int(method)
+    o.factor_loc = LOC_PINNED_HOST if factor == "host" else LOC_DEVICE
+    o.factor_batches = int(factor_batches)
     it = (ctypes.c_int32 * kk)()
     lam = (ctypes.c_double * kk)()
     info = TsvdInfo()
@@ -682,19 +705,25 @@ def tsvd_spmv(ctx: Context, csr: Csr, x, trans: int = 0, stream=None):
 
 
 def tsvd_sparse(ctx: Context, csr: Csr, k, eps, v0, max_iter=10000, fixed_iters=None, branch=0, hbm_budget=0,
-                stream=None, raise_not_converged=False):
-    """Whole t-SVD of a registered CSR matrix.  Returns (U, S, V, info)."""
+                stream=None, raise_not_converged=False, factor="device", factor_batches=1, queue_depth=2):
+    """Whole t-SVD of a registered CSR matrix.  factor="host" keeps the
+    iterated factor in pinned host memory (batched to the device for every
+    projection, factor_batches batches through queue_depth device buffers).
+    Returns (U, S, V, info)."""
     torch = _torch()
     m, n = csr.shape
     kk = min(m, n) if k == -1 else k
     right = (m > n) if branch == 1 else (m >= n)
     d = n if right else m
-    dev = csr._keep[0].device
+    dev = torch.device("cuda", ctx.device)
     _check_v0(v0, kk, d, dev)
-    U = _colmajor_out(m, kk, dev)
-    V = _colmajor_out(n, kk, dev)
+    U = _factor_out(m, kk, dev, factor if not right else "device")
+    V = _factor_out(n, kk, dev, factor if right else "device")
     S = torch.zeros(kk, dtype=torch.float64, device=dev)
     o, keep = _make_opts(ctx.lib, k, eps, v0, max_iter, fixed_iters, "auto", 0, hbm_budget, branch)
+    o.queue_depth = int(queue_depth)
+    o.factor_loc = LOC_PINNED_HOST if factor == "host" else LOC_DEVICE
+    o.factor_batches = int(factor_batches)
     it = (ctypes.c_int32 * kk)()
     lam = (ctypes.c_double * kk)()
     info = TsvdInfo()

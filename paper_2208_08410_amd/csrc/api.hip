@@ -16,6 +16,7 @@
 
 #include "ctx.h"
 #include "internal.h"
+#include "implicit.h"
 
 namespace tsvd {
 
@@ -131,6 +132,7 @@ tsvd_status tsvd_ctx_set_tuning(tsvd_ctx* ctx, const tsvd_tuning* t) {
     return fail(ctx, TSVD_ERR_INVALID_ARG, "team_kib must be 0 or in [8, 65536]");
   if (t->group_kchunk != 0 && (t->group_kchunk < 32 || t->group_kchunk > (1 << 20)))
     return fail(ctx, TSVD_ERR_INVALID_ARG, "group_kchunk must be 0 or in [32, 2^20]");
+  if (t->power_path != 0 && t->power_path != 1) return fail(ctx, TSVD_ERR_INVALID_ARG, "power_path must be 0 or 1");
   ctx->tuning = *t;
   return TSVD_OK;
 }
@@ -260,10 +262,76 @@ tsvd_status tsvd_gram_dense(tsvd_ctx* ctx, const void* A, int32_t dtype, int64_t
   return from_internal(ctx, rc, "tsvd_gram_dense");
 }
 
-// shared power-phase driver (workspace carved from `bump`)
-static tsvd_status run_power(tsvd_ctx* ctx, Bump& bump, void* B, int is_f64, int64_t d, int64_t ldb, int k,
-                             const tsvd_opts* o, double* X, int64_t ldx, const PowerPlan& pp, int* d_status,
-                             int* d_iters, double* d_lambda, int* d_fixed, hipStream_t stream) {
+// ---------------------------------------------------------------------------
+// power phase on an explicit Gram in the workspace: the on-chip persistent
+// kernel when its plan fits (and the tuning allows it), else the host-driven
+// loop of HBM-streamed products B x with deflation by projection
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+
+struct PhaseResult {
+  int kd = 0, conv = 1, rankdef = 0;
+  std::vector<int> iters;
+  std::vector<double> lams;
+};
+
+size_t power_ws_bytes(const PowerPlan& pp, int k) {
+  const size_t words = pp.xex_words + pp.pex_words + pp.vex_words + pp.wex_words;
+  return align256(words * 8) + align256((size_t)pp.G * 2 * (k + 2) * 8) + 4 * 256 + align256((size_t)k * 4) +
+         align256((size_t)k * 8) + align256((size_t)k * 4) + 1024;
+}
+
+// plans the on-chip kernel; false when the loop must run instead
+bool plan_onchip(tsvd_ctx* ctx, int eb, int64_t d, int k, PowerPlan* pp) {
+  if (ctx->tuning.power_path != 0 || d > 0x7fffffffLL) return false;
+  return power_plan(eb, (int)d, k, ctx->num_cu, ctx->max_lds, ctx->tuning.power_blocks, pp) == 0;
+}
+
+size_t phase_ws_bytes(bool onchip, const PowerPlan& pp, int64_t d, int k) {
+  return onchip ? power_ws_bytes(pp, k) : loop_ws_bytes(d, k);
+}
+
+// true when `need` bytes of workspace fit hbm_budget and the device's memory
+bool ws_fits(tsvd_ctx* ctx, size_t need, int64_t budget) {
+  if (budget > 0 && (int64_t)need > budget) return false;
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+    (void)hipGetLastError();
+    return true;
+  }
+  return need <= fr + ctx->ws_bytes;
+}
+
+tsvd_status power_phase(tsvd_ctx* ctx, Bump& bump, bool onchip, const PowerPlan& pp, void* B, int is_f64, int64_t d,
+                        int64_t ldb, int k, const tsvd_opts* o, double* X, int64_t ldx, PhaseResult* pr,
+                        hipStream_t stream) {
+  pr->iters.assign(k, 0);
+  pr->lams.assign(k, 0.0);
+  if (!onchip) {
+    LoopWs lw = loop_ws_take(bump, d, k);
+    GramOp op;
+    op.B = B;
+    op.b_f64 = is_f64;
+    op.d = d;
+    op.ldb = ldb;
+    DeviceFactor fac(X, ldx, d);
+    PowerLoopResult r;
+    int rc = implicit_power(op, fac, o, k, d, lw, &r, stream);
+    if (rc) return from_internal(ctx, rc, "power iteration (streamed Gram)");
+    if (r.nonfinite) return fail(ctx, TSVD_ERR_NONFINITE, "non-finite value in the Gram or the power iteration");
+    pr->kd = r.kdone;
+    pr->conv = r.all_conv ? 1 : 0;
+    pr->rankdef = r.rankdef ? 1 : 0;
+    pr->iters = r.iters;
+    pr->lams = r.lams;
+    return TSVD_OK;
+  }
+  int* d_status = (int*)bump.take(256);
+  int* d_iters = (int*)bump.take((size_t)k * 4);
+  double* d_lambda = (double*)bump.take((size_t)k * 8);
+  int* d_fixed = (int*)bump.take((size_t)k * 4);
   PowerArgs a;
   memset(&a, 0, sizeof a);
   a.B = B;
@@ -295,14 +363,48 @@ static tsvd_status run_power(tsvd_ctx* ctx, Bump& bump, void* B, int is_f64, int
   if (int rc = zero_bytes_launch(d_status, 16, stream)) return from_internal(ctx, rc, "clear status");
   int rc = power_launch(is_f64, pp, a, stream);
   if (rc == -2) return fail(ctx, TSVD_ERR_UNSUPPORTED, "power kernel does not fit on a CU");
-  return from_internal(ctx, rc, "power iteration");
+  if (rc) return from_internal(ctx, rc, "power iteration");
+  int hs[4];
+  if (hipMemcpyAsync(hs, d_status, 16, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      hipMemcpyAsync(pr->iters.data(), d_iters, (size_t)k * 4, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      hipMemcpyAsync(pr->lams.data(), d_lambda, (size_t)k * 8, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess)
+    return fail(ctx, TSVD_ERR_HIP, "power status readback: %s", hipGetErrorString(hipGetLastError()));
+  if (hs[2] == 1) return fail(ctx, TSVD_ERR_INTERNAL, "power iteration: a bounded wait timed out");
+  if (hs[2] == 2) return fail(ctx, TSVD_ERR_NONFINITE, "non-finite value in the Gram or the power iteration");
+  if (hs[2] == 3) return fail(ctx, TSVD_ERR_INVALID_ARG, "a start vector is zero");
+  pr->kd = hs[0];
+  pr->conv = hs[1];
+  pr->rankdef = hs[3];
+  return TSVD_OK;
 }
 
-static size_t power_ws_bytes(const PowerPlan& pp, int k) {
-  const size_t words = pp.xex_words + pp.pex_words + pp.vex_words + pp.wex_words;
-  return align256(words * 8) + align256((size_t)pp.G * 2 * (k + 2) * 8) + 4 * 256 + align256((size_t)k * 4) +
-         align256((size_t)k * 8) + align256((size_t)k * 4) + 1024;
+void fill_info(tsvd_info* info, const PhaseResult& pr, int k, bool right, tsvd_ctx* ctx, size_t need, int64_t h2d) {
+  if (!info) return;
+  info->k_done = pr.kd;
+  info->converged = pr.conv;
+  info->rank_deficient = pr.rankdef;
+  info->branch_right = right ? 1 : 0;
+  if (info->iters) memcpy(info->iters, pr.iters.data(), (size_t)k * 4);
+  if (info->lambda) memcpy(info->lambda, pr.lams.data(), (size_t)k * 8);
+  float t;
+  hipEventElapsedTime(&t, ctx->ev[0], ctx->ev[1]); info->t_gram_ms = t;
+  hipEventElapsedTime(&t, ctx->ev[1], ctx->ev[2]); info->t_eig_ms = t;
+  hipEventElapsedTime(&t, ctx->ev[2], ctx->ev[3]); info->t_final_ms = t;
+  hipEventElapsedTime(&t, ctx->ev[0], ctx->ev[3]); info->t_total_ms = t;
+  info->workspace_bytes = (int64_t)need;
+  info->h2d_bytes = h2d;
+  info->latency_ms = 0;
 }
+
+tsvd_status not_converged(tsvd_ctx* ctx, const PhaseResult& pr, const tsvd_opts* o) {
+  if (!pr.conv && !o->fixed_iters && o->eps > 0) return fail(ctx, TSVD_ERR_NOT_CONVERGED, "some triplet reached max_iter");
+  return TSVD_OK;
+}
+
+}  // namespace
+
+extern "C" {
 
 tsvd_status tsvd_power_gram(tsvd_ctx* ctx, void* B, int32_t dtype, int64_t d, int64_t ldb, const tsvd_opts* o,
                             double* X, int64_t ldx, tsvd_info* info, void* stream_) {
@@ -319,41 +421,26 @@ tsvd_status tsvd_power_gram(tsvd_ctx* ctx, void* B, int32_t dtype, int64_t d, in
   hipStream_t stream = (hipStream_t)stream_;
   const int is_f64 = dtype == TSVD_F64;
   PowerPlan pp;
-  if (power_plan(is_f64 ? 8 : 4, (int)d, k, ctx->num_cu, ctx->max_lds, ctx->tuning.power_blocks, &pp))
-    return fail(ctx, TSVD_ERR_UNSUPPORTED, "d=%lld too large for the LDS-resident iterate", (long long)d);
-  tsvd_status st = ensure_ws(ctx, power_ws_bytes(pp, k), o->hbm_budget);
+  const bool onchip = plan_onchip(ctx, is_f64 ? 8 : 4, d, k, &pp);
+  const size_t need = phase_ws_bytes(onchip, pp, d, k) + 1024;
+  tsvd_status st = ensure_ws(ctx, need, o->hbm_budget);
   if (st) return st;
   Bump bump(ctx->ws, ctx->ws_bytes);
-  int* d_status = (int*)bump.take(256);
-  int* d_iters = (int*)bump.take((size_t)k * 4);
-  double* d_lambda = (double*)bump.take((size_t)k * 8);
-  int* d_fixed = (int*)bump.take((size_t)k * 4);
   if (int rc = zero_cols_launch(X, ldx, d, k, stream)) return from_internal(ctx, rc, "clear X");
-  st = run_power(ctx, bump, B, is_f64, d, ldb, k, o, X, ldx, pp, d_status, d_iters, d_lambda, d_fixed, stream);
+  PhaseResult pr;
+  st = power_phase(ctx, bump, onchip, pp, B, is_f64, d, ldb, k, o, X, ldx, &pr, stream);
   if (st) return st;
-  int hs[4];
-  std::vector<int> hit(k);
-  std::vector<double> hl(k);
-  if (hipMemcpyAsync(hs, d_status, 16, hipMemcpyDeviceToHost, stream) != hipSuccess ||
-      hipMemcpyAsync(hit.data(), d_iters, (size_t)k * 4, hipMemcpyDeviceToHost, stream) != hipSuccess ||
-      hipMemcpyAsync(hl.data(), d_lambda, (size_t)k * 8, hipMemcpyDeviceToHost, stream) != hipSuccess ||
-      hipStreamSynchronize(stream) != hipSuccess)
-    return fail(ctx, TSVD_ERR_HIP, "power status readback: %s", hipGetErrorString(hipGetLastError()));
   if (info) {
-    info->k_done = hs[0];
-    info->converged = hs[1];
-    info->rank_deficient = hs[3];
+    info->k_done = pr.kd;
+    info->converged = pr.conv;
+    info->rank_deficient = pr.rankdef;
     info->branch_right = 1;
     info->latency_ms = 0;
-    if (info->iters) memcpy(info->iters, hit.data(), (size_t)k * 4);
-    if (info->lambda) memcpy(info->lambda, hl.data(), (size_t)k * 8);
+    info->workspace_bytes = (int64_t)need;
+    if (info->iters) memcpy(info->iters, pr.iters.data(), (size_t)k * 4);
+    if (info->lambda) memcpy(info->lambda, pr.lams.data(), (size_t)k * 8);
   }
-  if (hs[2] == 1) return fail(ctx, TSVD_ERR_INTERNAL, "power iteration: a bounded wait timed out");
-  if (hs[2] == 2) return fail(ctx, TSVD_ERR_NONFINITE, "non-finite value in the power iteration");
-  if (hs[2] == 3) return fail(ctx, TSVD_ERR_INVALID_ARG, "a start vector is zero");
-  if (!hs[1] && !o->fixed_iters && o->eps > 0)
-    return fail(ctx, TSVD_ERR_NOT_CONVERGED, "some triplet reached max_iter");
-  return TSVD_OK;
+  return not_converged(ctx, pr, o);
 }
 
 tsvd_status tsvd_finish_dense(tsvd_ctx* ctx, const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
@@ -403,16 +490,148 @@ tsvd_status tsvd_finish_dense_noalloc(tsvd_ctx* ctx, const void* A, int32_t dtyp
   return from_internal(ctx, rc, "finish scale (allocation-free)");
 }
 
+}  // extern "C"
+
+namespace {
+
+// Dense t-SVD without the Gram: Algorithm 2's product applied as
+// A^T (A x) (or A (A^T x)) every iteration (Equation 2 evaluated right to
+// left).  A in HBM (any dtype, both branches) or FP32 A in pinned host memory
+// (right branch; streamed once per iteration).  The iterated factor may sit
+// in pinned host memory (A in HBM only).
+tsvd_status dense_implicit(tsvd_ctx* ctx, const void* A, int32_t dtype, int32_t loc, int64_t m, int64_t n, int64_t lda,
+                           const tsvd_opts* o, int k, double* U, int64_t ldu, double* S, double* V, int64_t ldv,
+                           tsvd_info* info, hipStream_t s) {
+  const bool right = right_side(m, n, o->branch);
+  const int side = right ? TSVD_SIDE_RIGHT : TSVD_SIDE_LEFT;
+  const int64_t d = right ? n : m, e = right ? m : n;
+  const bool pinned = loc == TSVD_LOC_PINNED_HOST;
+  const bool host_x = o->factor_loc == TSVD_LOC_PINNED_HOST;
+  if (pinned && !right) return fail(ctx, TSVD_ERR_UNSUPPORTED, "pinned-host A needs the A^T A branch (m >= n)");
+  if (pinned && dtype != TSVD_F32) return fail(ctx, TSVD_ERR_UNSUPPORTED, "pinned-host A is FP32");
+  if (pinned && host_x) return fail(ctx, TSVD_ERR_UNSUPPORTED, "with A streamed from the host the factor stays on the device");
+  const int Q = o->queue_depth > 0 ? o->queue_depth : 2;
+  if (Q > 16 || o->factor_batches < 0) return fail(ctx, TSVD_ERR_INVALID_ARG, "queue_depth or factor_batches");
+  const int is_f64 = dtype == TSVD_F64;
+  double* X = right ? V : U;
+  const int64_t ldx = right ? ldv : ldu;
+  double* W = right ? U : V;
+  const int64_t ldw = right ? ldu : ldv;
+  if (host_x) {
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, X) != hipSuccess || attr.type != hipMemoryTypeHost) {
+      (void)hipGetLastError();
+      return fail(ctx, TSVD_ERR_INVALID_ARG, "factor_loc = PINNED_HOST needs %s in pinned host memory",
+                  right ? "V" : "U");
+    }
+  }
+  if (pinned) {
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, A) != hipSuccess || attr.type != hipMemoryTypeHost) {
+      (void)hipGetLastError();
+      return fail(ctx, TSVD_ERR_INVALID_ARG, "A is not pinned host memory (allocate it with hipHostMalloc / pin_memory)");
+    }
+  }
+  // batch rows of a pinned A: rows_per_block rounded up to 128, or 4 GiB of rows
+  int64_t R = 0;
+  if (pinned) {
+    R = o->rows_per_block > 0 ? ((o->rows_per_block + 127) / 128) * 128 : (((int64_t)4 << 30) / (n * 4)) / 128 * 128;
+    if (R < 128) R = 128;
+    if (R > m) R = m;
+  }
+  const int64_t nbatch = pinned ? (m + R - 1) / R : 0;
+  const int Qa = pinned ? (int)std::min<int64_t>(Q, nbatch) : 0;
+  const size_t buf_bytes = pinned ? align256((size_t)R * n * 4) : 0;
+  const size_t op_bytes =
+      align256((size_t)(pinned ? PinnedDenseOp::ws_doubles(m, n, R) : DenseOp::ws_doubles(m, n)) * 8);
+  const int64_t tiles_total = pinned ? (m + 127) / 128 + nbatch : finish_tiles(m, n, side);
+  const size_t fin_bytes = align256((size_t)(tiles_total + 2) * k * 8);
+  const int64_t RX = host_x ? HostFactor::round_rows(d, o->factor_batches > 0 ? o->factor_batches : 1) : 0;
+  const int Qx = host_x ? (int)std::min<int64_t>(Q, (d + RX - 1) / RX) : 0;
+  const size_t slot_bytes = host_x ? align256((size_t)RX * k * 8) : 0;
+  const size_t need = loop_ws_bytes(d, k) + (size_t)Qa * buf_bytes + op_bytes + fin_bytes + align256((size_t)d * 8) +
+                      (size_t)Qx * slot_bytes + 4096;
+  tsvd_status st = ensure_ws(ctx, need, o->hbm_budget);
+  if (st) return st;
+  Bump bump(ctx->ws, ctx->ws_bytes);
+  LoopWs lw = loop_ws_take(bump, d, k);
+  float* bufs[16];
+  for (int q = 0; q < Qa; q++) bufs[q] = (float*)bump.take(buf_bytes);
+  double* opws = (double*)bump.take(op_bytes);
+  double* ssq = (double*)bump.take(fin_bytes);
+  double* tmp = (double*)bump.take((size_t)d * 8);
+  double* slots[16];
+  for (int q = 0; q < Qx; q++) slots[q] = (double*)bump.take(slot_bytes);
+
+  DenseOp dop;
+  PinnedDenseOp pop;
+  if (pinned) {
+    if (pop.init((const float*)A, m, n, lda, R, Qa, bufs, opws, ctx->copy_stream))
+      return fail(ctx, TSVD_ERR_HIP, "batch pipeline events");
+  } else {
+    dop.setup(A, is_f64, m, n, lda, right, opws);
+  }
+  ImplicitOp& op = pinned ? (ImplicitOp&)pop : (ImplicitOp&)dop;
+  DeviceFactor dfac(X, ldx, d);
+  HostFactor hfac;
+  if (host_x && hfac.init(X, ldx, d, RX, Qx, k, slots, ctx->copy_stream))
+    return fail(ctx, TSVD_ERR_HIP, "factor pipeline events");
+  Factor& fac = host_x ? (Factor&)hfac : (Factor&)dfac;
+
+  hipEventRecord(ctx->ev[0], s);
+  if (zero_cols_launch(W, ldw, e, k, s) || zero_cols_launch(S, k, k, 1, s) ||
+      (!host_x && zero_cols_launch(X, ldx, d, k, s)))
+    return fail(ctx, TSVD_ERR_HIP, "clear outputs");
+  if (host_x) {
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(ctx, TSVD_ERR_HIP, "sync");
+    for (int j = 0; j < k; j++) memset(X + (int64_t)j * ldx, 0, (size_t)d * 8);
+  }
+  hipEventRecord(ctx->ev[1], s);
+  PowerLoopResult r;
+  int rc = implicit_power(op, fac, o, k, d, lw, &r, s);
+  if (rc) return from_internal(ctx, rc, "implicit power iteration");
+  if (r.nonfinite) return fail(ctx, TSVD_ERR_NONFINITE, "non-finite value in a product or a norm");
+  const int kd = r.kdone;
+  hipEventRecord(ctx->ev[2], s);
+  if (kd > 0) {
+    if (host_x) {
+      rc = finish_host_factor(op, X, ldx, d, W, ldw, e, S, kd, right, tmp, lw.partial, s);
+    } else if (pinned) {
+      int64_t tiles = 0;
+      rc = pop.finish(V, ldv, kd, U, ldu, ssq, &tiles, s);
+      if (!rc) rc = finish_sigma_launch(ssq, tiles, kd, S, s);
+      if (!rc) rc = finish_scale_sign_launch(U, ldu, m, S, V, ldv, n, U, ldu, m, kd, 1, ssq + tiles_total * k, s);
+    } else {
+      rc = finish_launch(is_f64, side, A, m, n, lda, X, ldx, kd, W, ldw, S, ssq, s);
+      if (!rc)
+        rc = finish_scale_sign_launch(W, ldw, e, S, V, ldv, n, U, ldu, m, kd, 1, ssq + finish_tiles(m, n, side) * k, s);
+    }
+    if (rc) return from_internal(ctx, rc, "finish");
+  }
+  hipEventRecord(ctx->ev[3], s);
+  if (hipStreamSynchronize(s) != hipSuccess) return fail(ctx, TSVD_ERR_HIP, "sync");
+  PhaseResult pr;
+  pr.kd = kd;
+  pr.conv = r.all_conv ? 1 : 0;
+  pr.rankdef = r.rankdef ? 1 : 0;
+  pr.iters = r.iters;
+  pr.lams = r.lams;
+  fill_info(info, pr, k, right, ctx, need, op.h2d_bytes() + fac.h2d_bytes());
+  if (info) info->t_gram_ms = 0.0;  // no Gram phase: the interval before the loop only clears the outputs
+  return not_converged(ctx, pr, o);
+}
+
 // Dense t-SVD of an FP32 A held in pinned host memory (Algorithm 3's
 // out-of-memory batching).  Rows are streamed in batches through
 // `queue_depth` device buffers: the copy stream fills buffer b % Q while the
 // compute stream runs the Gram (pass 1) or the FP64 finishing product (pass 2)
 // on the previous batch; events order reuse.  The power iteration runs on the
 // device-resident Gram between the passes, overlapped with the first copies of
-// pass 2.
-static tsvd_status dense_pinned(tsvd_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t lda, const tsvd_opts* o,
-                                int k, int mode, double* U, int64_t ldu, double* S, double* V, int64_t ldv,
-                                tsvd_info* info, hipStream_t s) {
+// pass 2.  auto_method: fall back to the implicit product when the Gram's
+// workspace does not fit.
+tsvd_status dense_pinned(tsvd_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t lda, const tsvd_opts* o, int k,
+                         int mode, bool auto_method, double* U, int64_t ldu, double* S, double* V, int64_t ldv,
+                         tsvd_info* info, hipStream_t s) {
   if (!right_side(m, n, o->branch))
     return fail(ctx, TSVD_ERR_UNSUPPORTED, "pinned-host input needs the A^T A branch (m >= n)");
   hipPointerAttribute_t attr;
@@ -440,13 +659,15 @@ static tsvd_status dense_pinned(tsvd_ctx* ctx, const float* A, int64_t m, int64_
             ctx->tuning.gram_chunks);
   const size_t part_bytes = sp_full.partial_bytes > sp_last.partial_bytes ? sp_full.partial_bytes : sp_last.partial_bytes;
   PowerPlan pp;
-  if (power_plan(4, (int)d, k, ctx->num_cu, ctx->max_lds, ctx->tuning.power_blocks, &pp))
-    return fail(ctx, TSVD_ERR_UNSUPPORTED, "n=%lld too large for the LDS-resident iterate", (long long)d);
+  const bool onchip = plan_onchip(ctx, 4, d, k, &pp);
   const int64_t tiles_total = (m + 127) / 128 + nbatch;  // finish row tiles, one partial tile per batch at most
   const size_t buf_bytes = align256((size_t)R * n * 4);
   const size_t b_bytes = align256((size_t)d * ldb * 4);
   const size_t ssq_bytes = align256((size_t)(tiles_total + 2) * k * 8);
-  const size_t need = (size_t)Q * buf_bytes + b_bytes + align256(part_bytes) + power_ws_bytes(pp, k) + ssq_bytes + 4096;
+  const size_t need =
+      (size_t)Q * buf_bytes + b_bytes + align256(part_bytes) + phase_ws_bytes(onchip, pp, d, k) + ssq_bytes + 4096;
+  if (auto_method && !ws_fits(ctx, need, o->hbm_budget))
+    return dense_implicit(ctx, A, TSVD_F32, TSVD_LOC_PINNED_HOST, m, n, lda, o, k, U, ldu, S, V, ldv, info, s);
   tsvd_status st = ensure_ws(ctx, need, o->hbm_budget);
   if (st) return st;
   Bump bump(ctx->ws, ctx->ws_bytes);
@@ -455,20 +676,19 @@ static tsvd_status dense_pinned(tsvd_ctx* ctx, const float* A, int64_t m, int64_
   void* B = bump.take(b_bytes);
   void* partial = bump.take(part_bytes);
   double* ssq = (double*)bump.take(ssq_bytes);
-  int* d_status = (int*)bump.take(256);
-  int* d_iters = (int*)bump.take((size_t)k * 4);
-  double* d_lambda = (double*)bump.take((size_t)k * 8);
-  int* d_fixed = (int*)bump.take((size_t)k * 4);
 
   hipEvent_t copied[16], consumed[16];
   int made = 0;
   auto cleanup = [&]() {
-    for (int i = 0; i < made; i++) { hipEventDestroy(copied[i]); hipEventDestroy(consumed[i]); }
+    for (int i = 0; i < made; i++) {
+      (void)hipEventDestroy(copied[i]);
+      (void)hipEventDestroy(consumed[i]);
+    }
   };
   for (; made < Q; made++) {
     if (hipEventCreateWithFlags(&copied[made], hipEventDisableTiming) != hipSuccess) { cleanup(); return fail(ctx, TSVD_ERR_HIP, "event"); }
     if (hipEventCreateWithFlags(&consumed[made], hipEventDisableTiming) != hipSuccess) {
-      hipEventDestroy(copied[made]);
+      (void)hipEventDestroy(copied[made]);
       cleanup();
       return fail(ctx, TSVD_ERR_HIP, "event");
     }
@@ -508,22 +728,15 @@ static tsvd_status dense_pinned(tsvd_ctx* ctx, const float* A, int64_t m, int64_
   const int64_t pre = nbatch < Q ? nbatch : Q;
   for (int64_t b = 0; b < pre && !rc; b++) rc = copy_batch(b, (int)(b % Q), true);
   if (rc) { cleanup(); return from_internal(ctx, rc, "prefetch"); }
-  st = run_power(ctx, bump, B, 0, d, ldb, k, o, V, ldv, pp, d_status, d_iters, d_lambda, d_fixed, s);
-  if (st) { cleanup(); return st; }
+  PhaseResult pr;
+  st = power_phase(ctx, bump, onchip, pp, B, 0, d, ldb, k, o, V, ldv, &pr, s);
+  if (st) {
+    (void)hipStreamSynchronize(cs);
+    cleanup();
+    return st;
+  }
   hipEventRecord(ctx->ev[2], s);
-  int hs[4];
-  if (hipMemcpyAsync(hs, d_status, 16, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
-    cleanup();
-    return fail(ctx, TSVD_ERR_HIP, "status readback: %s", hipGetErrorString(hipGetLastError()));
-  }
-  if (hs[2] != 0) {
-    hipStreamSynchronize(cs);
-    cleanup();
-    if (hs[2] == 1) return fail(ctx, TSVD_ERR_INTERNAL, "power iteration: a bounded wait timed out");
-    if (hs[2] == 2) return fail(ctx, TSVD_ERR_NONFINITE, "non-finite value in the Gram or the power iteration");
-    return fail(ctx, TSVD_ERR_INVALID_ARG, "a start vector is zero");
-  }
-  const int kd = hs[0];
+  const int kd = pr.kd;
   // ---- pass 2: U = A V (FP64), column sums of squares per row tile
   int64_t tile_off = 0;
   for (int64_t b = 0; b < nbatch && !rc && kd > 0; b++) {
@@ -542,31 +755,13 @@ static tsvd_status dense_pinned(tsvd_ctx* ctx, const float* A, int64_t m, int64_
   if (!rc && (hipStreamSynchronize(s) != hipSuccess || hipStreamSynchronize(cs) != hipSuccess)) rc = TSVD_ERR_HIP;
   cleanup();
   if (rc) return from_internal(ctx, rc, "pinned finish pass");
-  std::vector<int> hit(k);
-  std::vector<double> hl(k);
-  if (hipMemcpy(hit.data(), d_iters, (size_t)k * 4, hipMemcpyDeviceToHost) != hipSuccess ||
-      hipMemcpy(hl.data(), d_lambda, (size_t)k * 8, hipMemcpyDeviceToHost) != hipSuccess)
-    return fail(ctx, TSVD_ERR_HIP, "readback");
-  if (info) {
-    info->k_done = kd;
-    info->converged = hs[1];
-    info->rank_deficient = hs[3];
-    info->branch_right = 1;
-    if (info->iters) memcpy(info->iters, hit.data(), (size_t)k * 4);
-    if (info->lambda) memcpy(info->lambda, hl.data(), (size_t)k * 8);
-    float t;
-    hipEventElapsedTime(&t, ctx->ev[0], ctx->ev[1]); info->t_gram_ms = t;
-    hipEventElapsedTime(&t, ctx->ev[1], ctx->ev[2]); info->t_eig_ms = t;
-    hipEventElapsedTime(&t, ctx->ev[2], ctx->ev[3]); info->t_final_ms = t;
-    hipEventElapsedTime(&t, ctx->ev[0], ctx->ev[3]); info->t_total_ms = t;
-    info->workspace_bytes = (int64_t)need;
-    info->h2d_bytes = (int64_t)(m * n * 4) * (kd > 0 ? 2 : 1);
-    info->latency_ms = 0;
-  }
-  if (!hs[1] && !o->fixed_iters && o->eps > 0)
-    return fail(ctx, TSVD_ERR_NOT_CONVERGED, "some triplet reached max_iter");
-  return TSVD_OK;
+  fill_info(info, pr, k, true, ctx, need, (int64_t)(m * n * 4) * (kd > 0 ? 2 : 1));
+  return not_converged(ctx, pr, o);
 }
+
+}  // namespace
+
+extern "C" {
 
 tsvd_status tsvd_dense(tsvd_ctx* ctx, const void* A, int32_t dtype, int32_t loc, int64_t m, int64_t n, int64_t lda,
                        const tsvd_opts* o, double* U, int64_t ldu, double* S, double* V, int64_t ldv,
@@ -585,13 +780,22 @@ tsvd_status tsvd_dense(tsvd_ctx* ctx, const void* A, int32_t dtype, int32_t loc,
     for (int l = 0; l < k; l++)
       if (o->fixed_iters[l] < 1) return fail(ctx, TSVD_ERR_INVALID_ARG, "fixed_iters[%d] < 1", l);
   if (loc != TSVD_LOC_DEVICE && loc != TSVD_LOC_PINNED_HOST) return fail(ctx, TSVD_ERR_INVALID_ARG, "bad loc");
+  if (o->method < TSVD_METHOD_AUTO || o->method > TSVD_METHOD_IMPLICIT)
+    return fail(ctx, TSVD_ERR_INVALID_ARG, "bad method %d", o->method);
+  if (o->factor_loc != TSVD_LOC_DEVICE && o->factor_loc != TSVD_LOC_PINNED_HOST)
+    return fail(ctx, TSVD_ERR_INVALID_ARG, "bad factor_loc");
+  if (o->factor_loc == TSVD_LOC_PINNED_HOST && o->method == TSVD_METHOD_GRAM)
+    return fail(ctx, TSVD_ERR_INVALID_ARG, "a pinned-host factor needs the implicit product (method IMPLICIT or AUTO)");
+  hipSetDevice(ctx->device);
+  hipStream_t stream = (hipStream_t)stream_;
+  if (o->method == TSVD_METHOD_IMPLICIT || o->factor_loc == TSVD_LOC_PINNED_HOST)
+    return dense_implicit(ctx, A, dtype, loc, m, n, lda, o, k, U, ldu, S, V, ldv, info, stream);
   const int mode = gram_mode(o->gram, dtype);
   tsvd_status st = check_mode(ctx, mode, dtype);
   if (st) return st;
+  const bool auto_method = o->method == TSVD_METHOD_AUTO;
   if (loc == TSVD_LOC_PINNED_HOST)
-    return dense_pinned(ctx, (const float*)A, m, n, lda, o, k, mode, U, ldu, S, V, ldv, info, (hipStream_t)stream_);
-  hipSetDevice(ctx->device);
-  hipStream_t stream = (hipStream_t)stream_;
+    return dense_pinned(ctx, (const float*)A, m, n, lda, o, k, mode, auto_method, U, ldu, S, V, ldv, info, stream);
 
   const bool right = right_side(m, n, o->branch);
   const int side = right ? TSVD_SIDE_RIGHT : TSVD_SIDE_LEFT;
@@ -604,21 +808,18 @@ tsvd_status tsvd_dense(tsvd_ctx* ctx, const void* A, int32_t dtype, int32_t loc,
   SyrkPlan sp;
   syrk_plan(mode, d, K, o->rows_per_block, ctx->num_cu, &sp, ctx->tuning.gram_tile, ctx->tuning.gram_chunks);
   PowerPlan pp;
-  if (power_plan(eb, (int)d, k, ctx->num_cu, ctx->max_lds, ctx->tuning.power_blocks, &pp))
-    return fail(ctx, TSVD_ERR_UNSUPPORTED, "d=%lld too large for the LDS-resident iterate", (long long)d);
+  const bool onchip = plan_onchip(ctx, eb, d, k, &pp);
   const size_t b_bytes = align256((size_t)d * ldb * eb);
   const size_t fin_bytes = align256((size_t)finish_workspace_doubles(m, n, side, k) * 8);
-  const size_t need = b_bytes + align256(sp.partial_bytes) + power_ws_bytes(pp, k) + fin_bytes + 4096;
+  const size_t need = b_bytes + align256(sp.partial_bytes) + phase_ws_bytes(onchip, pp, d, k) + fin_bytes + 4096;
+  if (auto_method && !ws_fits(ctx, need, o->hbm_budget))
+    return dense_implicit(ctx, A, dtype, loc, m, n, lda, o, k, U, ldu, S, V, ldv, info, stream);
   st = ensure_ws(ctx, need, o->hbm_budget);
   if (st) return st;
   Bump bump(ctx->ws, ctx->ws_bytes);
   void* B = bump.take(b_bytes);
   void* partial = bump.take(sp.partial_bytes);
   double* ssq = (double*)bump.take(fin_bytes);
-  int* d_status = (int*)bump.take(256);
-  int* d_iters = (int*)bump.take((size_t)k * 4);
-  double* d_lambda = (double*)bump.take((size_t)k * 8);
-  int* d_fixed = (int*)bump.take((size_t)k * 4);
 
   double* X = right ? V : U;
   const int64_t ldx = right ? ldv : ldu;
@@ -633,17 +834,11 @@ tsvd_status tsvd_dense(tsvd_ctx* ctx, const void* A, int32_t dtype, int32_t loc,
   int rc = syrk_launch(mode, side, A, m, n, lda, sp, partial, B, ldb, 0, stream);
   if (rc) return from_internal(ctx, rc, "gram");
   hipEventRecord(ctx->ev[1], stream);
-  st = run_power(ctx, bump, B, is_f64, d, ldb, k, o, X, ldx, pp, d_status, d_iters, d_lambda, d_fixed, stream);
+  PhaseResult pr;
+  st = power_phase(ctx, bump, onchip, pp, B, is_f64, d, ldb, k, o, X, ldx, &pr, stream);
   if (st) return st;
   hipEventRecord(ctx->ev[2], stream);
-  int hs[4];
-  if (hipMemcpyAsync(hs, d_status, 16, hipMemcpyDeviceToHost, stream) != hipSuccess ||
-      hipStreamSynchronize(stream) != hipSuccess)
-    return fail(ctx, TSVD_ERR_HIP, "status readback: %s", hipGetErrorString(hipGetLastError()));
-  if (hs[2] == 1) return fail(ctx, TSVD_ERR_INTERNAL, "power iteration: a bounded wait timed out");
-  if (hs[2] == 2) return fail(ctx, TSVD_ERR_NONFINITE, "non-finite value in the Gram or the power iteration");
-  if (hs[2] == 3) return fail(ctx, TSVD_ERR_INVALID_ARG, "a start vector is zero");
-  const int kd = hs[0];
+  const int kd = pr.kd;
   if (kd > 0) {
     rc = finish_launch(is_f64, side, A, m, n, lda, X, ldx, kd, W, ldw, S, ssq, stream);
     if (rc) return from_internal(ctx, rc, "finish");
@@ -652,315 +847,10 @@ tsvd_status tsvd_dense(tsvd_ctx* ctx, const void* A, int32_t dtype, int32_t loc,
     if (rc) return from_internal(ctx, rc, "finish scale/sign");
   }
   hipEventRecord(ctx->ev[3], stream);
-  std::vector<int> hit(k);
-  std::vector<double> hl(k);
-  if (hipMemcpyAsync(hit.data(), d_iters, (size_t)k * 4, hipMemcpyDeviceToHost, stream) != hipSuccess ||
-      hipMemcpyAsync(hl.data(), d_lambda, (size_t)k * 8, hipMemcpyDeviceToHost, stream) != hipSuccess ||
-      hipStreamSynchronize(stream) != hipSuccess)
-    return fail(ctx, TSVD_ERR_HIP, "readback: %s", hipGetErrorString(hipGetLastError()));
-  if (info) {
-    info->k_done = kd;
-    info->converged = hs[1];
-    info->rank_deficient = hs[3];
-    info->branch_right = right ? 1 : 0;
-    if (info->iters) memcpy(info->iters, hit.data(), (size_t)k * 4);
-    if (info->lambda) memcpy(info->lambda, hl.data(), (size_t)k * 8);
-    float t;
-    hipEventElapsedTime(&t, ctx->ev[0], ctx->ev[1]); info->t_gram_ms = t;
-    hipEventElapsedTime(&t, ctx->ev[1], ctx->ev[2]); info->t_eig_ms = t;
-    hipEventElapsedTime(&t, ctx->ev[2], ctx->ev[3]); info->t_final_ms = t;
-    hipEventElapsedTime(&t, ctx->ev[0], ctx->ev[3]); info->t_total_ms = t;
-    info->workspace_bytes = (int64_t)need;
-    info->h2d_bytes = 0;
-    info->latency_ms = 0;
-  }
-  if (!hs[1] && !o->fixed_iters && o->eps > 0)
-    return fail(ctx, TSVD_ERR_NOT_CONVERGED, "some triplet reached max_iter");
-  return TSVD_OK;
-}
-
-// ---------------------------------------------------------------------------
-// sparse path
-// ---------------------------------------------------------------------------
-}  // extern "C"
-
-struct tsvd_csr {
-  int device = 0;
-  int64_t m = 0, n = 0, nnz = 0;
-  const int64_t* rowptr = nullptr;
-  const int32_t* col = nullptr;
-  const float* val = nullptr;
-  int64_t* colptr = nullptr;  // owned CSC copy
-  int32_t* rowidx = nullptr;
-  float* cval = nullptr;
-  // owned sliced tiles of A (from the CSR) and of A^T (from the CSC): dir 0 / 1
-  tsvd::TilePlan tp[2] = {};
-  int64_t* tptr[2] = {nullptr, nullptr};
-  uint32_t* tkey[2] = {nullptr, nullptr};
-  float* tval[2] = {nullptr, nullptr};
-};
-
-namespace {
-// y = A x (dir 0) or A^T x (dir 1) through the sliced tiles
-int csr_product(const tsvd_csr* c, int dir, const void* x, int x_is_f64, double* y, float* yf, hipStream_t s) {
-  return spmv_tiles_launch(c->tp[dir], c->tptr[dir], c->tkey[dir], c->tval[dir], dir == 0 ? c->m : c->n, x, x_is_f64,
-                           y, yf, s);
-}
-}  // namespace
-
-extern "C" {
-
-tsvd_status tsvd_csr_create(tsvd_ctx* ctx, int64_t m, int64_t n, int64_t nnz, const int64_t* rowptr,
-                            const int32_t* col, const float* val, tsvd_csr** out, void* stream_) {
-  if (!ctx) return TSVD_ERR_INVALID_ARG;
-  if (!out) return fail(ctx, TSVD_ERR_INVALID_ARG, "null out");
-  *out = nullptr;
-  if (m < 1 || n < 1 || nnz < 0) return fail(ctx, TSVD_ERR_INVALID_ARG, "bad shape m=%lld n=%lld nnz=%lld",
-                                              (long long)m, (long long)n, (long long)nnz);
-  if (n > 0x7fffffffLL || m > 0x7fffffffLL) return fail(ctx, TSVD_ERR_UNSUPPORTED, "int32 indices need m, n < 2^31");
-  if (!rowptr || (nnz > 0 && (!col || !val))) return fail(ctx, TSVD_ERR_INVALID_ARG, "null pointer");
-  hipSetDevice(ctx->device);
-  hipStream_t s = (hipStream_t)stream_;
-  int* d_bad = nullptr;
-  if (hipMalloc(&d_bad, 256) != hipSuccess) return fail(ctx, TSVD_ERR_OUT_OF_MEMORY, "hipMalloc");
-  int rc = csr_validate(rowptr, col, m, n, nnz, d_bad, s);
-  int hbad = 0;
-  if (rc == 0 && (hipMemcpyAsync(&hbad, d_bad, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
-                  hipStreamSynchronize(s) != hipSuccess))
-    rc = TSVD_ERR_HIP;
-  hipFree(d_bad);
-  if (rc) return from_internal(ctx, rc, "csr validation");
-  if (hbad) return fail(ctx, TSVD_ERR_INVALID_ARG, "CSR structure invalid (flags %d: 1 row pointers, 2 ends, 4 columns)",
-                        hbad);
-  tsvd_csr* c = new tsvd_csr();
-  c->device = ctx->device;
-  c->m = m; c->n = n; c->nnz = nnz;
-  c->rowptr = rowptr; c->col = col; c->val = val;
-  void* scratch = nullptr;
-  if (hipMalloc(&c->colptr, (size_t)(n + 1) * 8) != hipSuccess ||
-      hipMalloc(&c->rowidx, (size_t)(nnz > 0 ? nnz : 1) * 4) != hipSuccess ||
-      hipMalloc(&c->cval, (size_t)(nnz > 0 ? nnz : 1) * 4) != hipSuccess ||
-      hipMalloc(&scratch, csc_build_scratch_bytes(n)) != hipSuccess) {
-    (void)hipGetLastError();
-    hipFree(scratch);
-    tsvd_csr_destroy(c);
-    return fail(ctx, TSVD_ERR_OUT_OF_MEMORY, "allocating the CSC copy (%lld nonzeros)", (long long)nnz);
-  }
-  rc = csc_build(rowptr, col, val, m, n, nnz, c->colptr, c->rowidx, c->cval, scratch, s);
-  if (rc == 0 && hipStreamSynchronize(s) != hipSuccess) rc = TSVD_ERR_HIP;
-  hipFree(scratch);
-  if (rc) {
-    tsvd_csr_destroy(c);
-    return from_internal(ctx, rc, "CSC build");
-  }
-  // sliced tiles for both products: A from the CSR, A^T from the CSC
-  for (int dir = 0; dir < 2; dir++) {
-    const int64_t rows = dir == 0 ? m : n, cols = dir == 0 ? n : m;
-    if (tiles_plan(rows, cols, ctx->num_cu, ctx->tuning.sparse_row_bits, ctx->tuning.sparse_col_bits, &c->tp[dir])) {
-      tsvd_csr_destroy(c);
-      return fail(ctx, TSVD_ERR_INVALID_ARG, "sparse tile bits out of range");
-    }
-    const int64_t nt = c->tp[dir].nchunks * c->tp[dir].nslices;
-    void* tscr = nullptr;
-    if (hipMalloc(&c->tptr[dir], (size_t)(nt + 1) * 8) != hipSuccess ||
-        hipMalloc(&c->tkey[dir], (size_t)(nnz > 0 ? nnz : 1) * 4) != hipSuccess ||
-        hipMalloc(&c->tval[dir], (size_t)(nnz > 0 ? nnz : 1) * 4) != hipSuccess ||
-        hipMalloc(&tscr, tiles_scratch_bytes(c->tp[dir])) != hipSuccess) {
-      (void)hipGetLastError();
-      hipFree(tscr);
-      tsvd_csr_destroy(c);
-      return fail(ctx, TSVD_ERR_OUT_OF_MEMORY, "allocating the sparse tiles (%lld nonzeros)", (long long)nnz);
-    }
-    rc = dir == 0 ? tiles_build(rowptr, col, val, m, nnz, c->tp[0], c->tptr[0], c->tkey[0], c->tval[0], tscr, s)
-                  : tiles_build(c->colptr, c->rowidx, c->cval, n, nnz, c->tp[1], c->tptr[1], c->tkey[1], c->tval[1],
-                                tscr, s);
-    if (rc == 0 && hipStreamSynchronize(s) != hipSuccess) rc = TSVD_ERR_HIP;
-    hipFree(tscr);
-    if (rc) {
-      tsvd_csr_destroy(c);
-      return from_internal(ctx, rc, "tile build");
-    }
-  }
-  *out = c;
-  return TSVD_OK;
-}
-
-void tsvd_csr_destroy(tsvd_csr* c) {
-  if (!c) return;
-  hipSetDevice(c->device);
-  hipDeviceSynchronize();
-  hipFree(c->colptr);
-  for (int dir = 0; dir < 2; dir++) {
-    hipFree(c->tptr[dir]);
-    hipFree(c->tkey[dir]);
-    hipFree(c->tval[dir]);
-  }
-  hipFree(c->rowidx);
-  hipFree(c->cval);
-  delete c;
-}
-
-tsvd_status tsvd_csr_get_csc(tsvd_ctx* ctx, const tsvd_csr* c, int64_t* colptr, int32_t* rowidx, float* val,
-                             void* stream) {
-  if (!ctx) return TSVD_ERR_INVALID_ARG;
-  if (!c || !colptr || (c->nnz > 0 && (!rowidx || !val))) return fail(ctx, TSVD_ERR_INVALID_ARG, "null pointer");
-  hipStream_t s = (hipStream_t)stream;
-  if (hipMemcpyAsync(colptr, c->colptr, (size_t)(c->n + 1) * 8, hipMemcpyDeviceToDevice, s) != hipSuccess ||
-      (c->nnz > 0 && (hipMemcpyAsync(rowidx, c->rowidx, (size_t)c->nnz * 4, hipMemcpyDeviceToDevice, s) != hipSuccess ||
-                      hipMemcpyAsync(val, c->cval, (size_t)c->nnz * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)))
-    return fail(ctx, TSVD_ERR_HIP, "copy CSC");
-  return TSVD_OK;
-}
-
-tsvd_status tsvd_spmv(tsvd_ctx* ctx, const tsvd_csr* c, int32_t trans, const void* x, int32_t x_dtype, double* y,
-                      void* stream) {
-  if (!ctx) return TSVD_ERR_INVALID_ARG;
-  if (!c || !x || !y) return fail(ctx, TSVD_ERR_INVALID_ARG, "null pointer");
-  if (trans != 0 && trans != 1) return fail(ctx, TSVD_ERR_INVALID_ARG, "trans must be 0 or 1");
-  if (x_dtype != TSVD_F32 && x_dtype != TSVD_F64) return fail(ctx, TSVD_ERR_INVALID_ARG, "bad x dtype");
-  hipSetDevice(ctx->device);
-  int rc = csr_product(c, trans, x, x_dtype == TSVD_F64, y, nullptr, (hipStream_t)stream);
-  return from_internal(ctx, rc, "spmv");
-}
-
-tsvd_status tsvd_sparse(tsvd_ctx* ctx, const tsvd_csr* c, const tsvd_opts* o, double* U, int64_t ldu, double* S,
-                        double* V, int64_t ldv, tsvd_info* info, void* stream_) {
-  if (!ctx) return TSVD_ERR_INVALID_ARG;
-  if (!c || !o || !U || !S || !V || !o->v0) return fail(ctx, TSVD_ERR_INVALID_ARG, "null pointer");
-  const int64_t m = c->m, n = c->n;
-  if (ldu < m || ldv < n) return fail(ctx, TSVD_ERR_INVALID_ARG, "ldu < m or ldv < n");
-  const int64_t mn = m < n ? m : n;
-  const int k = o->k == -1 ? (int)mn : o->k;
-  if (k < 1 || k > mn) return fail(ctx, TSVD_ERR_INVALID_ARG, "k=%d outside [1, min(m, n)=%lld]", o->k, (long long)mn);
-  if (o->branch != 0 && o->branch != 1) return fail(ctx, TSVD_ERR_INVALID_ARG, "bad branch");
-  if (o->fixed_iters)
-    for (int l = 0; l < k; l++)
-      if (o->fixed_iters[l] < 1) return fail(ctx, TSVD_ERR_INVALID_ARG, "fixed_iters[%d] < 1", l);
-  hipSetDevice(ctx->device);
-  hipStream_t s = (hipStream_t)stream_;
-  const bool right = right_side(m, n, o->branch);
-  const int64_t d = right ? n : m, e = right ? m : n;
-  double* X = right ? V : U;
-  const int64_t ldx = right ? ldv : ldu;
-  double* W = right ? U : V;
-  const int64_t ldw = right ? ldu : ldv;
-  const int max_iter = o->max_iter > 0 ? o->max_iter : 10000;
-
-  const int64_t nb = proj_blocks(d > e ? d : e);
-  const size_t need = align256((size_t)d * 8) * 2 + align256((size_t)d * 4) + align256((size_t)e * 4) +
-                      align256((size_t)nb * (k + 2) * 8) + align256((size_t)(k + 8) * 8) * 2 + 4096;
-  tsvd_status st = ensure_ws(ctx, need, o->hbm_budget);
-  if (st) return st;
-  Bump bump(ctx->ws, ctx->ws_bytes);
-  double* x = (double*)bump.take((size_t)d * 8);    // current unit iterate (FP64)
-  double* w = (double*)bump.take((size_t)d * 8);    // product, projected in place
-  float* xf = (float*)bump.take((size_t)d * 4);     // FP32 copy gathered by the first product
-  float* tf = (float*)bump.take((size_t)e * 4);     // intermediate A x (or A^T x) in FP32
-  double* partial = (double*)bump.take((size_t)std::max<int64_t>(nb * (k + 2), 2 * (int64_t)k) * 8);
-  double* coef = (double*)bump.take((size_t)(k + 8) * 8);
-  double* scal = (double*)bump.take((size_t)(k + 8) * 8);
-
-  // right branch: t = A x, w = A^T t; left branch: t = A^T x, w = A t
-  const int dir1 = right ? 0 : 1, dir2 = right ? 1 : 0;
-
-  hipEventRecord(ctx->ev[0], s);
-  if (zero_cols_launch(U, ldu, m, k, s) || zero_cols_launch(V, ldv, n, k, s) || zero_cols_launch(S, k, k, 1, s))
-    return fail(ctx, TSVD_ERR_HIP, "clear outputs");
-  hipEventRecord(ctx->ev[1], s);
-  std::vector<int> iters(k, 0);
-  std::vector<double> lams(k, 0.0);
-  bool all_conv = true, rankdef = false;
-  int kdone = k;
-  int rc = 0;
-  for (int l = 0; l < k && !rc && !rankdef; l++) {
-    // start vector: x = v0_l / ||v0_l||, then x <- x - X (X^T x) (projected once, not renormalised)
-    const double* v0 = o->v0 + (int64_t)l * d;
-    if ((rc = sumsq_launch(v0, d, partial, scal, s))) break;
-    if ((rc = start_scale_launch(v0, d, scal, x, s))) break;
-    if (l > 0) {
-      if ((rc = proj_partials_launch(X, ldx, l, x, x, d, partial, coef, s))) break;
-      if ((rc = proj_apply_launch(X, ldx, l, coef, x, d, partial, scal + 1, s))) break;
-    }
-    if ((rc = to_float_launch(x, d, xf, s))) break;
-    const int fixed = o->fixed_iters ? o->fixed_iters[l] : (o->eps <= 0.0 ? max_iter : 0);
-    int it = 0;
-    double nrm = 0.0;
-    bool conv = false;
-    while (true) {
-      if ((rc = csr_product(c, dir1, xf, 0, nullptr, tf, s))) break;
-      if ((rc = csr_product(c, dir2, tf, 0, w, nullptr, s))) break;
-      it++;
-      if ((rc = proj_partials_launch(X, ldx, l, w, x, d, partial, coef, s))) break;
-      if ((rc = proj_apply_launch(X, ldx, l, coef, w, d, partial, scal, s))) break;
-      double h[2];
-      if (hipMemcpyAsync(&h[0], scal, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
-          hipMemcpyAsync(&h[1], coef + l + 1, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
-          hipStreamSynchronize(s) != hipSuccess) {
-        rc = TSVD_ERR_HIP;
-        break;
-      }
-      nrm = sqrt(h[0]);
-      if (!std::isfinite(nrm)) return fail(ctx, TSVD_ERR_NONFINITE, "non-finite value in the sparse product");
-      if (nrm == 0.0) { rankdef = true; kdone = l; break; }
-      bool stop;
-      if (fixed > 0) { stop = it >= fixed; conv = true; }
-      else {
-        conv = fabs(h[1]) / nrm >= 1.0 - o->eps;
-        stop = conv || it >= max_iter;
-      }
-      if ((rc = normalize_launch(w, d, 1.0 / nrm, x, xf, s))) break;
-      if (stop) break;
-    }
-    if (rc || rankdef) break;
-    if (!conv) all_conv = false;
-    iters[l] = it;
-    lams[l] = nrm;
-    // FP64 re-orthogonalisation against the earlier columns, then store column l
-    if (l > 0) {
-      if ((rc = proj_partials_launch(X, ldx, l, x, x, d, partial, coef, s))) break;
-      if ((rc = proj_apply_launch(X, ldx, l, coef, x, d, partial, scal, s))) break;
-    } else if ((rc = sumsq_launch(x, d, partial, scal, s))) break;
-    double hn;
-    if (hipMemcpyAsync(&hn, scal, 8, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
-      rc = TSVD_ERR_HIP;
-      break;
-    }
-    if (!(hn > 0.0)) { rankdef = true; kdone = l; break; }
-    if ((rc = normalize_launch(x, d, 1.0 / sqrt(hn), X + (int64_t)l * ldx, nullptr, s))) break;
-  }
-  if (rc) return from_internal(ctx, rc, "sparse power iteration");
-  hipEventRecord(ctx->ev[2], s);
-  // finish: W[:, j] = A X[:, j] (right) or A^T X[:, j] (left) with FP64 input,
-  // sigma_j = ||W[:, j]||, then scale and sign convention
-  for (int j = 0; j < kdone && !rc; j++) {
-    double* wj = W + (int64_t)j * ldw;
-    rc = csr_product(c, dir1, X + (int64_t)j * ldx, 1, wj, nullptr, s);
-    if (!rc) rc = sumsq_launch(wj, e, partial, S + j, s);
-  }
-  if (!rc && kdone > 0) rc = sqrt_inplace_launch(S, kdone, s);
-  if (!rc && kdone > 0) rc = finish_scale_sign_launch(W, ldw, e, S, V, ldv, n, U, ldu, m, kdone, 1, partial, s);
-  if (rc) return from_internal(ctx, rc, "sparse finish");
-  hipEventRecord(ctx->ev[3], s);
-  if (hipStreamSynchronize(s) != hipSuccess) return fail(ctx, TSVD_ERR_HIP, "sync");
-  if (info) {
-    info->k_done = kdone;
-    info->converged = all_conv ? 1 : 0;
-    info->rank_deficient = rankdef ? 1 : 0;
-    info->branch_right = right ? 1 : 0;
-    if (info->iters) memcpy(info->iters, iters.data(), (size_t)k * 4);
-    if (info->lambda) memcpy(info->lambda, lams.data(), (size_t)k * 8);
-    float t;
-    info->t_gram_ms = 0.0;
-    hipEventElapsedTime(&t, ctx->ev[1], ctx->ev[2]); info->t_eig_ms = t;
-    hipEventElapsedTime(&t, ctx->ev[2], ctx->ev[3]); info->t_final_ms = t;
-    hipEventElapsedTime(&t, ctx->ev[0], ctx->ev[3]); info->t_total_ms = t;
-    info->workspace_bytes = (int64_t)need;
-    info->h2d_bytes = 0;
-    info->latency_ms = 0;
-  }
-  if (!all_conv && !o->fixed_iters && o->eps > 0)
-    return fail(ctx, TSVD_ERR_NOT_CONVERGED, "some triplet reached max_iter");
-  return TSVD_OK;
+  if (hipStreamSynchronize(stream) != hipSuccess)
+    return fail(ctx, TSVD_ERR_HIP, "sync: %s", hipGetErrorString(hipGetLastError()));
+  fill_info(info, pr, k, right, ctx, need, 0);
+  return not_converged(ctx, pr, o);
 }
 
 }  // extern "C"

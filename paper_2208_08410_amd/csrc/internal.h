@@ -139,8 +139,12 @@ size_t tiles_scratch_bytes(const TilePlan& t);
 // tptr: nchunks * nslices + 1 int64; key, tval: nnz each
 int tiles_build(const int64_t* ptr, const int32_t* idx, const float* val, int64_t rows, int64_t nnz,
                 const TilePlan& t, int64_t* tptr, uint32_t* key, float* tval, void* scratch, hipStream_t s);
+// y = A x over row chunks [c0, c0 + nch); key / val hold the entries from
+// tptr[c0 * nslices] on, whose absolute position is `base` (0 when the arrays
+// hold the whole matrix)
 int spmv_tiles_launch(const TilePlan& t, const int64_t* tptr, const uint32_t* key, const float* val, int64_t rows,
-                      const void* x, int x_is_f64, double* y, float* yf, hipStream_t s);
+                      const void* x, int x_is_f64, double* y, float* yf, int64_t base, int64_t c0, int64_t nch,
+                      hipStream_t s);
 int64_t proj_blocks(int64_t d);
 int proj_partials_launch(const double* V, int64_t ldv, int l, const double* w, const double* x, int64_t d,
                          double* partial, double* out, hipStream_t s);

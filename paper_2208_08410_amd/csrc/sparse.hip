@@ -16,6 +16,7 @@
 //   reduce_partials       fixed-order sum of block partials (one block)
 #include "common.h"
 #include "internal.h"
+#include "implicit.h"
 
 namespace tsvd {
 
@@ -304,6 +305,29 @@ int proj_apply_launch(const double* V, int64_t ldv, int l, const double* coef, d
   const int64_t nb = proj_blocks(d);
   hipLaunchKernelGGL(proj_apply_kernel, dim3((unsigned)nb), dim3(PB), 0, s, V, ldv, l, coef, w, d, partial);
   hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(256), 0, s, partial, nb, 1, out);
+  TSVD_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int proj_partials_part_launch(const double* V, int64_t ldv, int l, const double* w, const double* x, int64_t rows,
+                              double* partial, hipStream_t s) {
+  static_assert(PROWS == kProjRows, "host batches of the factor align with the projection blocks");
+  hipLaunchKernelGGL(proj_partials_kernel, dim3((unsigned)proj_blocks(rows)), dim3(PB), 0, s, V, ldv, l, w, x, rows,
+                     partial);
+  TSVD_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int proj_apply_part_launch(const double* V, int64_t ldv, int l, const double* coef, double* w, int64_t rows,
+                           double* partial, hipStream_t s) {
+  hipLaunchKernelGGL(proj_apply_kernel, dim3((unsigned)proj_blocks(rows)), dim3(PB), 0, s, V, ldv, l, coef, w, rows,
+                     partial);
+  TSVD_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int reduce_partials_launch(const double* partial, int64_t nb, int P, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(256), 0, s, partial, nb, P, out);
   TSVD_HIP_TRY(hipGetLastError());
   return 0;
 }

@@ -736,7 +736,7 @@ int syrk_plan(int mode, int64_t d, int64_t K, int64_t rows_per_block, int num_cu
   } else {
     const int64_t target = (BM == 256 ? 8 : 4) * (int64_t)num_cu;  // workgroups per CU: 1 for 256 tiles, 2 else
     S = (target + p->T - 1) / p->T;
-    S = ((S + 7) / 8) * 8;
+    if (S > 1) S = ((S + 7) / 8) * 8;  // whole XCD rounds; a Gram with enough tiles takes one chunk
     const int64_t maxS = (K + 4 * BK - 1) / (4 * BK);  // at least 4 k-stages per chunk
     if (S > maxS) S = maxS;
     if (S > 256) S = 256;

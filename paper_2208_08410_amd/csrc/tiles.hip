@@ -17,6 +17,7 @@
 // Products are exact in FP64; the sums use a fixed order (a segmented scan
 // over 64 lanes on DPP, then per-wave boundary rows added by one thread in
 // wave order), so results are deterministic.
+#include "../../include/tsvd.h"
 #include "common.h"
 #include "internal.h"
 
@@ -94,12 +95,12 @@ constexpr int TW = 8;  // waves per workgroup of the tiled product
 template <typename XT>
 __global__ __launch_bounds__(TW * 64) void spmv_tiles_kernel(const int64_t* tptr, const uint32_t* key, const float* val,
                                                          int64_t rows, int rbits, int cbits, int64_t ns, const XT* x,
-                                                         double* y, float* yf) {
+                                                         double* y, float* yf, int64_t base, int64_t c_off) {
   extern __shared__ double yl[];  // 2^rbits
   __shared__ int brow[2 * TW];
   __shared__ double bval[2 * TW];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t c = blockIdx.x;
+  const int64_t c = blockIdx.x + c_off;
   const int RH = 1 << rbits;
   const int64_t r0 = (int64_t)c << rbits;
   const int nrow = (int)min((int64_t)RH, rows - r0);
@@ -107,7 +108,7 @@ __global__ __launch_bounds__(TW * 64) void spmv_tiles_kernel(const int64_t* tptr
   for (int i = threadIdx.x; i < RH; i += TW * 64) yl[i] = 0.0;
   __syncthreads();
   for (int64_t s = 0; s < ns; s++) {
-    const int64_t a = tptr[c * ns + s], b = tptr[c * ns + s + 1];
+    const int64_t a = tptr[c * ns + s] - base, b = tptr[c * ns + s + 1] - base;  // entries of this batch's arrays
     const int64_t n = b - a;
     if (n == 0) continue;  // uniform
     const XT* xs = x + (s << cbits);
@@ -243,14 +244,17 @@ int tiles_build(const int64_t* ptr, const int32_t* idx, const float* val, int64_
 }
 
 int spmv_tiles_launch(const TilePlan& t, const int64_t* tptr, const uint32_t* key, const float* val, int64_t rows,
-                      const void* x, int x_is_f64, double* y, float* yf, hipStream_t s) {
+                      const void* x, int x_is_f64, double* y, float* yf, int64_t base, int64_t c0, int64_t nch,
+                      hipStream_t s) {
+  if (nch <= 0) return 0;
+  if (c0 < 0 || c0 + nch > t.nchunks) return TSVD_ERR_INTERNAL;
   const size_t lds = ((size_t)1 << t.rbits) * 8;
   if (x_is_f64)
-    hipLaunchKernelGGL((spmv_tiles_kernel<double>), dim3((unsigned)t.nchunks), dim3(TW * 64), lds, s, tptr, key, val,
-                       rows, t.rbits, t.cbits, t.nslices, (const double*)x, y, yf);
+    hipLaunchKernelGGL((spmv_tiles_kernel<double>), dim3((unsigned)nch), dim3(TW * 64), lds, s, tptr, key, val, rows,
+                       t.rbits, t.cbits, t.nslices, (const double*)x, y, yf, base, c0);
   else
-    hipLaunchKernelGGL((spmv_tiles_kernel<float>), dim3((unsigned)t.nchunks), dim3(TW * 64), lds, s, tptr, key, val, rows,
-                       t.rbits, t.cbits, t.nslices, (const float*)x, y, yf);
+    hipLaunchKernelGGL((spmv_tiles_kernel<float>), dim3((unsigned)nch), dim3(TW * 64), lds, s, tptr, key, val, rows,
+                       t.rbits, t.cbits, t.nslices, (const float*)x, y, yf, base, c0);
   TSVD_HIP_TRY(hipGetLastError());
   return 0;
 }

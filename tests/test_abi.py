@@ -77,9 +77,10 @@ LAYOUT_C = r"""
 int main(void) {
   F(tsvd_opts, k) F(tsvd_opts, eps) F(tsvd_opts, max_iter) F(tsvd_opts, fixed_iters) F(tsvd_opts, v0)
   F(tsvd_opts, gram) F(tsvd_opts, rows_per_block) F(tsvd_opts, hbm_budget) F(tsvd_opts, branch)
-  F(tsvd_opts, queue_depth) Z(tsvd_opts)
+  F(tsvd_opts, queue_depth) F(tsvd_opts, method) F(tsvd_opts, factor_loc) F(tsvd_opts, factor_batches)
+  Z(tsvd_opts)
   F(tsvd_tuning, gram_tile) F(tsvd_tuning, gram_chunks) F(tsvd_tuning, power_blocks) F(tsvd_tuning, team_kib)
-  F(tsvd_tuning, group_kchunk) F(tsvd_tuning, sparse_row_bits) F(tsvd_tuning, sparse_col_bits) F(tsvd_tuning, reserved)
+  F(tsvd_tuning, group_kchunk) F(tsvd_tuning, sparse_row_bits) F(tsvd_tuning, sparse_col_bits) F(tsvd_tuning, power_path)
   Z(tsvd_tuning)
   F(tsvd_info, k_done) F(tsvd_info, iters) F(tsvd_info, lambda) F(tsvd_info, t_gram_ms) F(tsvd_info, h2d_bytes) F(tsvd_info, latency_ms)
   Z(tsvd_info)
