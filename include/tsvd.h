@@ -353,7 +353,32 @@ typedef struct tsvd_csr tsvd_csr;
 tsvd_status tsvd_csr_create(tsvd_ctx* ctx, int64_t m, int64_t n, int64_t nnz, const int64_t* rowptr,
                             const int32_t* col, const float* val, tsvd_csr** out, void* stream);
 
-/* Free the handle's CSC copy.  NULL is ignored. */
+/* Register an m x n CSR matrix held in PINNED HOST memory (rowptr int64
+ * [m+1], col int32 [nnz], val FP32 [nnz]; hipHostMalloc / pinned torch
+ * tensors), for matrices kept out of HBM: the paper's out-of-memory case of
+ * degree 1 (Sec. III, Sec. V-C).  The arrays are read only during this call.
+ * The sliced tiles of A and of A^T are built on the device batch by batch
+ * (whole row chunks of at most batch_bytes of tiles per batch, 0 = 512 MiB;
+ * A^T's batches are gathered by streaming the CSR once per batch of its
+ * columns) and kept in pinned host memory owned by the handle (16 bytes per
+ * nonzero).  Every product then streams its tiles to the device through
+ * queue_depth device slots (0 = 2, at most 16) on the handle's copy stream,
+ * while the previous slot's product runs; the handle holds those slots
+ * (queue_depth x the largest batch x 8 bytes) and the tile pointers on the
+ * device.  Products, tsvd_spmv and tsvd_sparse give bitwise the results of a
+ * device handle of the same matrix (same tiles, same order).
+ * tsvd_csr_get_csc is UNSUPPORTED on such a handle.  Structure errors return
+ * INVALID_ARG as for tsvd_csr_create.  Synchronises `stream`. */
+tsvd_status tsvd_csr_create_pinned(tsvd_ctx* ctx, int64_t m, int64_t n, int64_t nnz, const int64_t* rowptr,
+                                   const int32_t* col, const float* val, int64_t batch_bytes, int32_t queue_depth,
+                                   tsvd_csr** out, void* stream);
+
+/* Where a handle's tiles live (*loc: TSVD_LOC_DEVICE or TSVD_LOC_PINNED_HOST),
+ * how many row batches a product of A streams (0 for device handles), and
+ * the device bytes the handle holds.  Any output may be NULL. */
+tsvd_status tsvd_csr_info(const tsvd_csr* csr, int32_t* loc, int64_t* batches, int64_t* device_bytes);
+
+/* Free the handle's CSC copy and tiles.  NULL is ignored. */
 void tsvd_csr_destroy(tsvd_csr* csr);
 
 /* Copy the CSC transpose into caller DEVICE buffers: colptr int64 [n+1],

@@ -32,6 +32,7 @@ __all__ = [
     "get_tuning",
     "Csr",
     "tsvd_csr_create",
+    "tsvd_csr_create_pinned",
     "tsvd_csr_get_csc",
     "tsvd_spmv",
     "tsvd_sparse",
@@ -219,6 +220,10 @@ def load_library():
     lib.tsvd_ctx_get_tuning.restype = ctypes.c_int
     lib.tsvd_csr_create.argtypes = [vp, i64, i64, i64, vp, vp, vp, ctypes.POINTER(vp), vp]
     lib.tsvd_csr_create.restype = ctypes.c_int
+    lib.tsvd_csr_create_pinned.argtypes = [vp, i64, i64, i64, vp, vp, vp, i64, i32, ctypes.POINTER(vp), vp]
+    lib.tsvd_csr_create_pinned.restype = ctypes.c_int
+    lib.tsvd_csr_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    lib.tsvd_csr_info.restype = ctypes.c_int
     lib.tsvd_csr_destroy.argtypes = [vp]
     lib.tsvd_csr_destroy.restype = None
     lib.tsvd_csr_get_csc.argtypes = [vp, vp, vp, vp, vp, vp]
@@ -638,27 +643,43 @@ class Server:
 
 
 class Csr:
-    """A registered CSR matrix (device arrays are borrowed: this object keeps
-    references to them) plus the library's CSC copy."""
+    """A registered CSR matrix.  Device arrays are borrowed (this object keeps
+    references to them) and the library adds its CSC copy and tiles in HBM.
+    Pinned host arrays (``pin_memory()``) give a handle whose tiles stay in
+    pinned host memory and are streamed to the device for every product
+    (batch_bytes of tiles per batch, queue_depth device slots)."""
 
-    def __init__(self, ctx: Context, rowptr, col, val, shape, stream=None):
+    def __init__(self, ctx: Context, rowptr, col, val, shape, stream=None, batch_bytes: int = 0,
+                 queue_depth: int = 0):
         torch = _torch()
         m, n = int(shape[0]), int(shape[1])
         if rowptr.dtype != torch.int64 or col.dtype != torch.int32 or val.dtype != torch.float32:
             raise TypeError("CSR arrays must be int64 rowptr, int32 col, float32 val")
+        pinned = not rowptr.is_cuda
         for t in (rowptr, col, val):
-            if not t.is_cuda or not t.is_contiguous():
-                raise ValueError("CSR arrays must be contiguous device tensors")
+            if not t.is_contiguous() or (t.is_cuda if pinned else not t.is_cuda):
+                raise ValueError("CSR arrays must be contiguous, all device tensors or all pinned host tensors")
+            if pinned and not t.is_pinned():
+                raise ValueError("host CSR arrays must be pinned (tensor.pin_memory())")
         if rowptr.numel() != m + 1 or col.numel() != val.numel():
             raise ValueError("rowptr must have m + 1 entries and col/val the same length")
-        self.ctx, self.shape, self.nnz = ctx, (m, n), int(col.numel())
-        self._keep = (rowptr, col, val)
+        self.ctx, self.shape, self.nnz, self.pinned = ctx, (m, n), int(col.numel()), pinned
+        self._keep = (rowptr, col, val) if not pinned else ()
         h = ctypes.c_void_p()
-        st = ctx.lib.tsvd_csr_create(ctx.handle, m, n, self.nnz, ctypes.c_void_p(rowptr.data_ptr()),
-                                     ctypes.c_void_p(col.data_ptr()), ctypes.c_void_p(val.data_ptr()), ctypes.byref(h),
-                                     _stream(stream))
+        ptrs = (ctypes.c_void_p(rowptr.data_ptr()), ctypes.c_void_p(col.data_ptr()), ctypes.c_void_p(val.data_ptr()))
+        if pinned:
+            st = ctx.lib.tsvd_csr_create_pinned(ctx.handle, m, n, self.nnz, *ptrs, int(batch_bytes), int(queue_depth),
+                                                ctypes.byref(h), _stream(stream))
+        else:
+            st = ctx.lib.tsvd_csr_create(ctx.handle, m, n, self.nnz, *ptrs, ctypes.byref(h), _stream(stream))
         ctx.check(st)
         self.handle = h
+
+    def info(self) -> dict:
+        loc, nb, dev = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64()
+        self.ctx.check(self.ctx.lib.tsvd_csr_info(self.handle, ctypes.byref(loc), ctypes.byref(nb), ctypes.byref(dev)))
+        return {"loc": "pinned_host" if loc.value == LOC_PINNED_HOST else "device", "batches": nb.value,
+                "device_bytes": dev.value}
 
     def close(self):
         if getattr(self, "handle", None):
@@ -676,10 +697,15 @@ def tsvd_csr_create(ctx: Context, rowptr, col, val, shape, stream=None) -> Csr:
     return Csr(ctx, rowptr, col, val, shape, stream)
 
 
+def tsvd_csr_create_pinned(ctx: Context, rowptr, col, val, shape, batch_bytes=0, queue_depth=0, stream=None) -> Csr:
+    """A CSR handle whose tiles stay in pinned host memory (arrays: pinned host tensors)."""
+    return Csr(ctx, rowptr, col, val, shape, stream, batch_bytes, queue_depth)
+
+
 def tsvd_csr_get_csc(ctx: Context, csr: Csr, stream=None):
     """(colptr int64 [n+1], rowidx int32 [nnz], val float32 [nnz]) of the CSC copy."""
     torch = _torch()
-    dev = csr._keep[0].device
+    dev = torch.device("cuda", ctx.device)
     m, n = csr.shape
     cp = torch.empty(n + 1, dtype=torch.int64, device=dev)
     ri = torch.empty(max(csr.nnz, 1), dtype=torch.int32, device=dev)

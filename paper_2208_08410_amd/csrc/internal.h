@@ -124,6 +124,16 @@ int csr_validate(const int64_t* rowptr, const int32_t* col, int64_t m, int64_t n
 size_t csc_build_scratch_bytes(int64_t n);
 int csc_build(const int64_t* rowptr, const int32_t* col, const float* val, int64_t m, int64_t n, int64_t nnz,
               int64_t* colptr, int32_t* rowidx, float* cval, void* scratch, hipStream_t s);
+// pieces of a batched CSC build (pinned-host matrices): column counts,
+// scatter of one row batch's entries with columns in [j0, j1) into the
+// sub-matrix's CSC, per-column sort by row, pointer rebasing and offsets
+int csc_count_launch(const int32_t* col, int64_t nnz, unsigned long long* cnt, hipStream_t s);
+int csc_fill_range_launch(const int64_t* rowptr, const int32_t* col, const float* val, int64_t rows, int64_t row0,
+                          int64_t j0, int64_t j1, const int64_t* sub_ptr, unsigned long long* fill, int32_t* rowidx,
+                          float* cval, hipStream_t s);
+int csc_sort_launch(const int64_t* colptr, int64_t n, int32_t* rowidx, float* cval, hipStream_t s);
+int rebase_launch(const int64_t* in, int64_t count, int64_t* out, hipStream_t s);
+int offset_launch(const int64_t* in, int64_t count, int64_t add, int64_t* out, hipStream_t s);
 // exclusive scan of n counts into out[0..n] (out[n] = total); bsum: (n + 1023) / 1024 + 1 entries
 int scan_counts(const unsigned long long* cnt, int64_t n, unsigned long long* bsum, int64_t* out, int64_t total,
                 hipStream_t s);

@@ -111,6 +111,40 @@ __global__ void csc_fill_kernel(const int64_t* rowptr, const int32_t* col, const
   }
 }
 
+// the entries of a batch of rows whose column lies in [j0, j1), scattered
+// into their column of the sub-matrix A[:, j0:j1] (CSC, column pointers
+// sub_ptr relative to its first entry); rows are numbered from row0
+__global__ void csc_fill_range_kernel(const int64_t* rowptr, const int32_t* col, const float* val, int64_t rows,
+                                      int64_t row0, int64_t j0, int64_t j1, const int64_t* sub_ptr,
+                                      unsigned long long* fill, int32_t* rowidx, float* cval) {
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+  const int lane = threadIdx.x & 63;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
+  for (int64_t r = wave; r < rows; r += nw) {
+    for (int64_t e = rowptr[r] + lane; e < rowptr[r + 1]; e += 64) {
+      const int64_t c = col[e];
+      if (c < j0 || c >= j1) continue;
+      const unsigned long long p = atomicAdd(fill + (c - j0), 1ull);
+      const int64_t pos = sub_ptr[c - j0] + (int64_t)p;
+      rowidx[pos] = (int32_t)(row0 + r);
+      cval[pos] = val[e];
+    }
+  }
+}
+
+// out[i] = in[i] - in[0] for i < count (pointer arrays of a batch made relative to its first entry)
+__global__ void rebase_kernel(const int64_t* in, int64_t count, int64_t* out) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t b = in[0];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) out[i] = in[i] - b;
+}
+
+// out[i] = in[i] + add
+__global__ void offset_kernel(const int64_t* in, int64_t count, int64_t add, int64_t* out) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) out[i] = in[i] + add;
+}
+
 // insertion sort of each column's (row, value) pairs by row; one thread per
 // column (columns hold a few dozen entries in the target workloads).
 __global__ void csc_sort_kernel(const int64_t* colptr, int64_t n, int32_t* rowidx, float* cval) {
@@ -285,6 +319,42 @@ int csc_build(const int64_t* rowptr, const int32_t* col, const float* val, int64
   hipLaunchKernelGGL(csc_fill_kernel, dim3(grid_for(m * 64, 256, 65536)), dim3(256), 0, s, rowptr, col, val, m,
                      colptr, fill, rowidx, cval);
   hipLaunchKernelGGL(csc_sort_kernel, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, colptr, n, rowidx, cval);
+  TSVD_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int csc_count_launch(const int32_t* col, int64_t nnz, unsigned long long* cnt, hipStream_t s) {
+  if (nnz <= 0) return 0;
+  hipLaunchKernelGGL(csc_count_kernel, dim3(grid_for(nnz, 256, 65536)), dim3(256), 0, s, col, nnz, cnt);
+  TSVD_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int csc_fill_range_launch(const int64_t* rowptr, const int32_t* col, const float* val, int64_t rows, int64_t row0,
+                          int64_t j0, int64_t j1, const int64_t* sub_ptr, unsigned long long* fill, int32_t* rowidx,
+                          float* cval, hipStream_t s) {
+  if (rows <= 0) return 0;
+  hipLaunchKernelGGL(csc_fill_range_kernel, dim3(grid_for(rows * 64, 256, 65536)), dim3(256), 0, s, rowptr, col, val,
+                     rows, row0, j0, j1, sub_ptr, fill, rowidx, cval);
+  TSVD_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int csc_sort_launch(const int64_t* colptr, int64_t n, int32_t* rowidx, float* cval, hipStream_t s) {
+  if (n <= 0) return 0;
+  hipLaunchKernelGGL(csc_sort_kernel, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, colptr, n, rowidx, cval);
+  TSVD_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int rebase_launch(const int64_t* in, int64_t count, int64_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(rebase_kernel, dim3(grid_for(count, 256, 65536)), dim3(256), 0, s, in, count, out);
+  TSVD_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int offset_launch(const int64_t* in, int64_t count, int64_t add, int64_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(offset_kernel, dim3(grid_for(count, 256, 65536)), dim3(256), 0, s, in, count, add, out);
   TSVD_HIP_TRY(hipGetLastError());
   return 0;
 }

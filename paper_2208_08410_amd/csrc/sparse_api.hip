@@ -35,10 +35,10 @@ struct tsvd_csr {
   uint32_t* tkey[2] = {nullptr, nullptr};
   float* tval[2] = {nullptr, nullptr};
   // pinned handles: batch b of direction dir covers row chunks
-  // [bchunk[dir][b], bchunk[dir][b + 1]); its entries are hptr[dir][c0 * ns] ..
-  // hptr[dir][c1 * ns] (host copy of tptr)
+  // [bchunk[dir][b], bchunk[dir][b + 1]) and entries [bentry[dir][b],
+  // bentry[dir][b + 1]) of the host tile arrays
   std::vector<int64_t> bchunk[2];
-  std::vector<int64_t> hptr[2];
+  std::vector<int64_t> bentry[2];
   int Q = 0;
   int64_t slot_entries = 0;
   uint32_t* skey[16] = {};
@@ -60,14 +60,13 @@ int csr_product(tsvd_csr* c, int dir, const void* x, int x_is_f64, double* y, fl
                              c->tp[dir].nchunks, s);
   // pinned: batch b of row chunks is copied into slot b % Q while the previous
   // batch's product runs; the rows of y it covers are written by that product
-  const int64_t ns = c->tp[dir].nslices;
   TSVD_HIP_TRY(hipEventRecord(c->start_ev, s));  // x is ready on s
   TSVD_HIP_TRY(hipStreamWaitEvent(c->cs, c->start_ev, 0));
   const std::vector<int64_t>& bc = c->bchunk[dir];
   for (size_t b = 0; b + 1 < bc.size(); b++) {
     const int q = (int)(b % c->Q);
     const int64_t c0 = bc[b], c1 = bc[b + 1];
-    const int64_t e0 = c->hptr[dir][c0 * ns], e1 = c->hptr[dir][c1 * ns];
+    const int64_t e0 = c->bentry[dir][b], e1 = c->bentry[dir][b + 1];
     if (c->used[q]) TSVD_HIP_TRY(hipStreamWaitEvent(c->cs, c->consumed[q], 0));
     if (e1 > e0) {
       TSVD_HIP_TRY(hipMemcpyAsync(c->skey[q], c->tkey[dir] + e0, (size_t)(e1 - e0) * 4, hipMemcpyHostToDevice, c->cs));
@@ -100,6 +99,27 @@ struct SparseOp : ImplicitOp {
   int first(const double* x, double* w, hipStream_t s) override { return csr_product(c, dir1, x, 1, w, nullptr, s); }
   int64_t h2d_bytes() const override { return c->h2d - h2d0; }
 };
+
+// greedy batches of whole row chunks holding at most `cap` entries each (a
+// chunk larger than cap gets a batch of its own); ent(c) = entries of chunk c
+template <typename F>
+void chunk_batches(int64_t nchunks, int64_t cap, F ent, std::vector<int64_t>* bc, std::vector<int64_t>* be) {
+  bc->assign(1, 0);
+  be->assign(1, 0);
+  int64_t cur = 0, e = 0;
+  for (int64_t ch = 0; ch < nchunks; ch++) {
+    const int64_t k = ent(ch);
+    if (ch > bc->back() && cur + k > cap) {
+      bc->push_back(ch);
+      be->push_back(e);
+      cur = 0;
+    }
+    cur += k;
+    e += k;
+  }
+  bc->push_back(nchunks);
+  be->push_back(e);
+}
 
 }  // namespace
 
@@ -177,6 +197,286 @@ tsvd_status tsvd_csr_create(tsvd_ctx* ctx, int64_t m, int64_t n, int64_t nnz, co
     }
   }
   *out = c;
+  return TSVD_OK;
+}
+
+tsvd_status tsvd_csr_create_pinned(tsvd_ctx* ctx, int64_t m, int64_t n, int64_t nnz, const int64_t* rowptr,
+                                   const int32_t* col, const float* val, int64_t batch_bytes, int32_t queue_depth,
+                                   tsvd_csr** out, void* stream_) {
+  if (!ctx) return TSVD_ERR_INVALID_ARG;
+  if (!out) return fail(ctx, TSVD_ERR_INVALID_ARG, "null out");
+  *out = nullptr;
+  if (m < 1 || n < 1 || nnz < 0) return fail(ctx, TSVD_ERR_INVALID_ARG, "bad shape m=%lld n=%lld nnz=%lld",
+                                              (long long)m, (long long)n, (long long)nnz);
+  if (n > 0x7fffffffLL || m > 0x7fffffffLL) return fail(ctx, TSVD_ERR_UNSUPPORTED, "int32 indices need m, n < 2^31");
+  if (!rowptr || (nnz > 0 && (!col || !val))) return fail(ctx, TSVD_ERR_INVALID_ARG, "null pointer");
+  if (batch_bytes < 0 || queue_depth < 0 || queue_depth > 16)
+    return fail(ctx, TSVD_ERR_INVALID_ARG, "batch_bytes < 0 or queue_depth outside [0, 16]");
+  for (const void* p : {(const void*)rowptr, (const void*)col, (const void*)val}) {
+    if (!p) continue;
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, p) != hipSuccess || attr.type != hipMemoryTypeHost) {
+      (void)hipGetLastError();
+      return fail(ctx, TSVD_ERR_INVALID_ARG, "the CSR arrays must be pinned host memory");
+    }
+  }
+  if (rowptr[0] != 0 || rowptr[m] != nnz)
+    return fail(ctx, TSVD_ERR_INVALID_ARG, "CSR structure invalid (flags 2: ends)");
+  hipSetDevice(ctx->device);
+  hipStream_t s = (hipStream_t)stream_;
+  tsvd_csr* c = new tsvd_csr();
+  c->device = ctx->device;
+  c->loc = TSVD_LOC_PINNED_HOST;
+  c->m = m; c->n = n; c->nnz = nnz;
+  c->rowptr = rowptr; c->col = col; c->val = val;
+  c->Q = queue_depth > 0 ? queue_depth : 2;
+  const int64_t cap = std::max<int64_t>(1, (batch_bytes > 0 ? batch_bytes : ((int64_t)512 << 20)) / 8);
+  for (int dir = 0; dir < 2; dir++) {
+    const int64_t rows = dir == 0 ? m : n, cols = dir == 0 ? n : m;
+    if (tiles_plan(rows, cols, ctx->num_cu, ctx->tuning.sparse_row_bits, ctx->tuning.sparse_col_bits, &c->tp[dir])) {
+      tsvd_csr_destroy(c);
+      return fail(ctx, TSVD_ERR_INVALID_ARG, "sparse tile bits out of range");
+    }
+  }
+  // row pointers at chunk boundaries must be monotone before the host sizes copies by them
+  const int rb0 = c->tp[0].rbits;
+  for (int64_t ch = 0; ch < c->tp[0].nchunks; ch++) {
+    const int64_t a = rowptr[ch << rb0], b = rowptr[std::min(m, (ch + 1) << rb0)];
+    if (a < 0 || b < a || b > nnz) {
+      tsvd_csr_destroy(c);
+      return fail(ctx, TSVD_ERR_INVALID_ARG, "CSR structure invalid (flags 1: row pointers)");
+    }
+  }
+  chunk_batches(c->tp[0].nchunks, cap,
+                [&](int64_t ch) { return rowptr[std::min(m, (ch + 1) << rb0)] - rowptr[ch << rb0]; }, &c->bchunk[0],
+                &c->bentry[0]);
+  // ---- device staging for the build
+  int64_t max_rows = 1, max_ent0 = 1, max_ch = 1;
+  for (size_t b = 0; b + 1 < c->bchunk[0].size(); b++) {
+    const int64_t r0 = c->bchunk[0][b] << rb0, r1 = std::min(m, c->bchunk[0][b + 1] << rb0);
+    max_rows = std::max(max_rows, r1 - r0);
+    max_ent0 = std::max(max_ent0, c->bentry[0][b + 1] - c->bentry[0][b]);
+    max_ch = std::max(max_ch, c->bchunk[0][b + 1] - c->bchunk[0][b]);
+  }
+  int rc = 0;
+  const int64_t ns0 = c->tp[0].nslices, ns1 = c->tp[1].nslices;
+  int64_t *d_rp_raw = nullptr, *d_rp = nullptr, *d_colptr = nullptr, *d_tptr_b = nullptr, *d_sub = nullptr;
+  int32_t* d_col = nullptr;
+  float* d_val = nullptr;
+  unsigned long long *d_cnt = nullptr, *d_bsum = nullptr;
+  int* d_bad = nullptr;
+  std::vector<void*> staged;
+  auto dalloc = [&](void** p, size_t bytes) {
+    if (rc) return;
+    if (hipMalloc(p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      *p = nullptr;
+      rc = TSVD_ERR_OUT_OF_MEMORY;
+      return;
+    }
+    staged.push_back(*p);
+  };
+  auto release = [&]() {
+    (void)hipStreamSynchronize(s);
+    for (void* p : staged) (void)hipFree(p);
+    staged.clear();
+  };
+  dalloc((void**)&d_rp_raw, (size_t)(max_rows + 1) * 8);
+  dalloc((void**)&d_rp, (size_t)(max_rows + 1) * 8);
+  dalloc((void**)&d_col, (size_t)max_ent0 * 4);
+  dalloc((void**)&d_val, (size_t)max_ent0 * 4);
+  dalloc((void**)&d_cnt, (size_t)(n + 1) * 8);
+  dalloc((void**)&d_bsum, (size_t)((n + 1023) / 1024 + 2) * 8);
+  dalloc((void**)&d_colptr, (size_t)(n + 1) * 8);
+  dalloc((void**)&d_bad, 256);
+  if (!rc) {
+    for (int dir = 0; dir < 2; dir++) {
+      if (hipMalloc(&c->tptr[dir], (size_t)(c->tp[dir].nchunks * c->tp[dir].nslices + 1) * 8) != hipSuccess ||
+          hipHostMalloc((void**)&c->tkey[dir], (size_t)std::max<int64_t>(nnz, 1) * 4, 0) != hipSuccess ||
+          hipHostMalloc((void**)&c->tval[dir], (size_t)std::max<int64_t>(nnz, 1) * 4, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        rc = TSVD_ERR_OUT_OF_MEMORY;
+      }
+    }
+  }
+  if (rc) {
+    release();
+    tsvd_csr_destroy(c);
+    return fail(ctx, TSVD_ERR_OUT_OF_MEMORY, "allocating the staging and host tile arrays (%lld nonzeros)",
+                (long long)nnz);
+  }
+  // tile staging, sized below for the larger direction
+  uint32_t* d_tkey = nullptr;
+  float* d_tval = nullptr;
+  void* d_tscr = nullptr;
+  int hbad = 0;
+  auto upload_rows = [&](size_t b) -> int {  // row batch b of the CSR -> d_rp (rebased), d_col, d_val
+    const int64_t r0 = c->bchunk[0][b] << rb0, r1 = std::min(m, c->bchunk[0][b + 1] << rb0);
+    const int64_t e0 = c->bentry[0][b], e1 = c->bentry[0][b + 1];
+    TSVD_HIP_TRY(hipMemcpyAsync(d_rp_raw, rowptr + r0, (size_t)(r1 - r0 + 1) * 8, hipMemcpyHostToDevice, s));
+    if (e1 > e0) {
+      TSVD_HIP_TRY(hipMemcpyAsync(d_col, col + e0, (size_t)(e1 - e0) * 4, hipMemcpyHostToDevice, s));
+      TSVD_HIP_TRY(hipMemcpyAsync(d_val, val + e0, (size_t)(e1 - e0) * 4, hipMemcpyHostToDevice, s));
+    }
+    return rebase_launch(d_rp_raw, r1 - r0 + 1, d_rp, s);
+  };
+  // ---- pass 1: tiles of A, batch by batch; column counts on the way
+  rc = zero_bytes_launch(d_cnt, (size_t)(n + 1) * 8, s);
+  if (!rc) {
+    dalloc((void**)&d_tkey, (size_t)max_ent0 * 4);
+    dalloc((void**)&d_tval, (size_t)max_ent0 * 4);
+    TilePlan tb = c->tp[0];
+    tb.nchunks = max_ch;
+    dalloc(&d_tscr, tiles_scratch_bytes(tb));
+    dalloc((void**)&d_tptr_b, (size_t)(max_ch * ns0 + 1) * 8);
+  }
+  for (size_t b = 0; !rc && b + 1 < c->bchunk[0].size(); b++) {
+    const int64_t c0 = c->bchunk[0][b], c1 = c->bchunk[0][b + 1];
+    const int64_t r0 = c0 << rb0, r1 = std::min(m, c1 << rb0);
+    const int64_t e0 = c->bentry[0][b], ent = c->bentry[0][b + 1] - e0;
+    if ((rc = upload_rows(b))) break;
+    // the structure is checked before anything indexes through it
+    if ((rc = csr_validate(d_rp, d_col, r1 - r0, n, ent, d_bad, s))) break;
+    if (hipMemcpyAsync(&hbad, d_bad, 4, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+      rc = TSVD_ERR_HIP;
+      break;
+    }
+    if (hbad) break;
+    if ((rc = csc_count_launch(d_col, ent, d_cnt, s))) break;
+    TilePlan tb = c->tp[0];
+    tb.nchunks = c1 - c0;
+    if ((rc = tiles_build(d_rp, d_col, d_val, r1 - r0, ent, tb, d_tptr_b, d_tkey, d_tval, d_tscr, s))) break;
+    if ((rc = offset_launch(d_tptr_b, (c1 - c0) * ns0 + 1, e0, c->tptr[0] + c0 * ns0, s))) break;
+    if (ent > 0 && (hipMemcpyAsync(c->tkey[0] + e0, d_tkey, (size_t)ent * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                    hipMemcpyAsync(c->tval[0] + e0, d_tval, (size_t)ent * 4, hipMemcpyDeviceToHost, s) != hipSuccess)) {
+      rc = TSVD_ERR_HIP;
+      break;
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) {  // the staging is reused by the next batch
+      rc = TSVD_ERR_HIP;
+      break;
+    }
+  }
+  if (!rc && hbad) {
+    release();
+    tsvd_csr_destroy(c);
+    return fail(ctx, TSVD_ERR_INVALID_ARG, "CSR structure invalid (flags %d: 1 row pointers, 2 ends, 4 columns)", hbad);
+  }
+  // ---- column pointers, then tiles of A^T: per batch of A^T row chunks
+  // (columns [j0, j1) of A), the whole CSR is streamed again and the entries
+  // of those columns are gathered into a CSC of the sub-matrix, sorted by row
+  std::vector<int64_t> colptr_h;
+  if (!rc) rc = scan_counts(d_cnt, n, d_bsum, d_colptr, nnz, s);
+  if (!rc) {
+    colptr_h.resize(n + 1);
+    if (hipMemcpyAsync(colptr_h.data(), d_colptr, (size_t)(n + 1) * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      rc = TSVD_ERR_HIP;
+  }
+  const int rb1 = c->tp[1].rbits;
+  int64_t max_ent1 = 1, max_ch1 = 1, max_cols = 1;
+  if (!rc) {
+    chunk_batches(c->tp[1].nchunks, cap,
+                  [&](int64_t ch) { return colptr_h[std::min(n, (ch + 1) << rb1)] - colptr_h[ch << rb1]; },
+                  &c->bchunk[1], &c->bentry[1]);
+    for (size_t b = 0; b + 1 < c->bchunk[1].size(); b++) {
+      const int64_t j0 = c->bchunk[1][b] << rb1, j1 = std::min(n, c->bchunk[1][b + 1] << rb1);
+      max_cols = std::max(max_cols, j1 - j0);
+      max_ent1 = std::max(max_ent1, c->bentry[1][b + 1] - c->bentry[1][b]);
+      max_ch1 = std::max(max_ch1, c->bchunk[1][b + 1] - c->bchunk[1][b]);
+    }
+  }
+  int32_t* d_rowidx = nullptr;
+  float* d_cval = nullptr;
+  unsigned long long* d_fill = nullptr;
+  if (!rc) {  // tile staging of pass 1 -> sized for A^T's batches
+    (void)hipStreamSynchronize(s);
+    for (void** p : {(void**)&d_tkey, (void**)&d_tval, &d_tscr, (void**)&d_tptr_b}) {
+      staged.erase(std::remove(staged.begin(), staged.end(), *p), staged.end());
+      (void)hipFree(*p);
+      *p = nullptr;
+    }
+    TilePlan tb = c->tp[1];
+    tb.nchunks = max_ch1;
+    dalloc((void**)&d_tkey, (size_t)max_ent1 * 4);
+    dalloc((void**)&d_tval, (size_t)max_ent1 * 4);
+    dalloc(&d_tscr, tiles_scratch_bytes(tb));
+    dalloc((void**)&d_tptr_b, (size_t)(max_ch1 * ns1 + 1) * 8);
+  }
+  dalloc((void**)&d_rowidx, (size_t)max_ent1 * 4);
+  dalloc((void**)&d_cval, (size_t)max_ent1 * 4);
+  dalloc((void**)&d_fill, (size_t)max_cols * 8);
+  dalloc((void**)&d_sub, (size_t)(max_cols + 1) * 8);
+  for (size_t b = 0; !rc && b + 1 < c->bchunk[1].size(); b++) {
+    const int64_t c0 = c->bchunk[1][b], c1 = c->bchunk[1][b + 1];
+    const int64_t j0 = c0 << rb1, j1 = std::min(n, c1 << rb1);
+    const int64_t f0 = c->bentry[1][b], ent = c->bentry[1][b + 1] - f0;
+    if ((rc = rebase_launch(d_colptr + j0, j1 - j0 + 1, d_sub, s))) break;
+    if ((rc = zero_bytes_launch(d_fill, (size_t)(j1 - j0) * 8, s))) break;
+    for (size_t rbt = 0; !rc && rbt + 1 < c->bchunk[0].size(); rbt++) {
+      const int64_t r0 = c->bchunk[0][rbt] << rb0, r1 = std::min(m, c->bchunk[0][rbt + 1] << rb0);
+      if ((rc = upload_rows(rbt))) break;
+      rc = csc_fill_range_launch(d_rp, d_col, d_val, r1 - r0, r0, j0, j1, d_sub, d_fill, d_rowidx, d_cval, s);
+    }
+    if (rc) break;
+    if ((rc = csc_sort_launch(d_sub, j1 - j0, d_rowidx, d_cval, s))) break;
+    TilePlan tb = c->tp[1];
+    tb.nchunks = c1 - c0;
+    if ((rc = tiles_build(d_sub, d_rowidx, d_cval, j1 - j0, ent, tb, d_tptr_b, d_tkey, d_tval, d_tscr, s))) break;
+    if ((rc = offset_launch(d_tptr_b, (c1 - c0) * ns1 + 1, f0, c->tptr[1] + c0 * ns1, s))) break;
+    if (ent > 0 && (hipMemcpyAsync(c->tkey[1] + f0, d_tkey, (size_t)ent * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                    hipMemcpyAsync(c->tval[1] + f0, d_tval, (size_t)ent * 4, hipMemcpyDeviceToHost, s) != hipSuccess)) {
+      rc = TSVD_ERR_HIP;
+      break;
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) rc = TSVD_ERR_HIP;
+  }
+  release();
+  if (rc) {
+    tsvd_csr_destroy(c);
+    if (rc == TSVD_ERR_OUT_OF_MEMORY) return fail(ctx, TSVD_ERR_OUT_OF_MEMORY, "allocating the build staging");
+    return from_internal(ctx, rc, "pinned tile build");
+  }
+  // ---- the streaming pipeline: Q device slots of the largest batch, events, a copy stream
+  c->slot_entries = std::max(max_ent0, max_ent1);
+  for (int q = 0; q < c->Q; q++) {
+    if (hipMalloc(&c->skey[q], (size_t)c->slot_entries * 4) != hipSuccess ||
+        hipMalloc(&c->sval[q], (size_t)c->slot_entries * 4) != hipSuccess) {
+      (void)hipGetLastError();
+      tsvd_csr_destroy(c);
+      return fail(ctx, TSVD_ERR_OUT_OF_MEMORY, "allocating %d streaming slots of %lld entries", c->Q,
+                  (long long)c->slot_entries);
+    }
+  }
+  bool ok = hipStreamCreateWithFlags(&c->cs, hipStreamNonBlocking) == hipSuccess &&
+            hipEventCreateWithFlags(&c->start_ev, hipEventDisableTiming) == hipSuccess;
+  for (; ok && c->made < c->Q; c->made++) {
+    if (hipEventCreateWithFlags(&c->copied[c->made], hipEventDisableTiming) != hipSuccess) { ok = false; break; }
+    if (hipEventCreateWithFlags(&c->consumed[c->made], hipEventDisableTiming) != hipSuccess) {
+      (void)hipEventDestroy(c->copied[c->made]);
+      ok = false;
+      break;
+    }
+  }
+  if (!ok) {
+    tsvd_csr_destroy(c);
+    return fail(ctx, TSVD_ERR_HIP, "streaming pipeline");
+  }
+  *out = c;
+  return TSVD_OK;
+}
+
+tsvd_status tsvd_csr_info(const tsvd_csr* c, int32_t* loc, int64_t* batches, int64_t* device_bytes) {
+  if (!c) return TSVD_ERR_INVALID_ARG;
+  if (loc) *loc = c->loc;
+  if (batches) *batches = c->loc == TSVD_LOC_PINNED_HOST ? (int64_t)(c->bchunk[0].size() - 1) : 0;
+  if (device_bytes) {
+    int64_t b = 0;
+    for (int dir = 0; dir < 2; dir++) b += (c->tp[dir].nchunks * c->tp[dir].nslices + 1) * 8;
+    if (c->loc == TSVD_LOC_DEVICE) b += c->nnz * 8 * 2 + c->nnz * 8 + (c->n + 1) * 8;
+    else b += (int64_t)c->Q * c->slot_entries * 8;
+    *device_bytes = b;
+  }
   return TSVD_OK;
 }
 
