@@ -54,7 +54,15 @@ def parse():
     ap.add_argument("--compare-fp32", type=int, default=1, help="also time the plain FP32 Gram mode")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--seed", type=int, default=2)
-    ap.add_argument("--workload", default="dense", choices=["dense", "serve", "stream", "sparse", "batch"])
+    ap.add_argument("--workload", default="dense", choices=["dense", "serve", "stream", "sparse", "batch", "oom"])
+    ap.add_argument("--legs", default="serve,stream",
+                    help="dense: extra legs run after the headline workload (comma list of serve, stream; '' = none)")
+    ap.add_argument("--leg-window", type=float, default=8.0, help="serve leg: seconds of measured arrivals")
+    ap.add_argument("--leg-stream-m", type=int, default=1_000_000, help="stream leg: rows of the pinned-host A")
+    ap.add_argument("--oom-n", type=int, default=8_388_608, help="oom: m = n of the CSR matrix")
+    ap.add_argument("--oom-per-row", type=float, default=50.0, help="oom: mean nonzeros per row")
+    ap.add_argument("--oom-k", type=int, default=8)
+    ap.add_argument("--oom-iters", type=int, default=10, help="oom: fixed iterations per triplet")
     ap.add_argument("--stream-m", type=int, default=2_000_000, help="stream: rows of the pinned-host A")
     ap.add_argument("--stream-n", type=int, default=8192)
     ap.add_argument("--stream-k", type=int, default=32)
@@ -342,6 +350,12 @@ def batch_main(a):
 
 
 def serve_main(a):
+    out = serve_run(a)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def serve_run(a):
     """Serving workload: Poisson arrivals into the library's request server."""
     import numpy as np
     import torch
@@ -438,8 +452,8 @@ def serve_main(a):
         shapes = [x[4] for x in meas]
         ks = [(x[3], int(sum(x[1]["iters"]))) for x in meas]
         out["cpu_baseline"] = serve_cpu_baseline(shapes, ks, eps, a.seed)
-    print(json.dumps(out), flush=True)
-    return 0
+    del pool
+    return out
 
 
 def progress(msg):
@@ -466,6 +480,12 @@ def pinned_empty(rows, cols):
 
 
 def stream_main(a):
+    out = stream_run(a)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def stream_run(a):
     """Out-of-HBM dense workload: A in pinned host memory, streamed in row
     batches (pass 1: Gram; pass 2: finishing product), spiked Gaussian rows."""
     import numpy as np
@@ -532,6 +552,13 @@ def stream_main(a):
         "frac_of_plain_copy": gbs / copy_gbs,
         "h2d_bytes": info["h2d_bytes"],
         "phase_ms": {"gram_pass": info["t_gram_ms"], "power": info["t_eig_ms"], "finish_pass": info["t_final_ms"]},
+        "gram_pass_gbs": m * n * 4 / (info["t_gram_ms"] * 1e-3) / 1e9,
+        "overlap": {"copy_ms": info["t_stream_copy_ms"], "compute_ms": info["t_stream_compute_ms"],
+                    "overlapped_ms": info["t_stream_overlap_ms"],
+                    "frac_of_compute_hidden": info["t_stream_overlap_ms"] / max(info["t_stream_compute_ms"], 1e-9),
+                    "frac_of_copy_overlapped": info["t_stream_overlap_ms"] / max(info["t_stream_copy_ms"], 1e-9),
+                    "note": "Gram pass: per-batch HIP event intervals on the copy stream and the compute stream "
+                            "(the library's own events); overlapped = time both streams were busy at once"},
         "iters_total": int(sum(info["iters"])),
         "sigma_top": [float(x) for x in Sh[:4]],
         "theta_top": [float(x) for x in theta[:4]],
@@ -540,8 +567,7 @@ def stream_main(a):
     ctx.close()
     del A
     _hip().hipHostFree(ptr)
-    print(json.dumps(out), flush=True)
-    return 0
+    return out
 
 
 def sparse_main(a):
@@ -627,6 +653,82 @@ def sparse_main(a):
     return 0
 
 
+def oom_main(a):
+    """Out-of-memory sweep of the sparse path, the paper's degree-1 experiment
+    (Sec. VI-B, fixed iterations): A's tiles in HBM and the heavy co-factor V
+    in pinned host memory, batched to the device in n_b row batches through
+    q_s device buffers for every projection.  Reports time and peak device
+    memory per (n_b, q_s) with q_s <= n_b, next to V on the device, and one run
+    with A's tiles streamed from pinned host memory as well."""
+    import numpy as np
+    import torch
+
+    import paper_2208_08410_amd as P
+    import synth
+
+    dev = torch.device("cuda:0")
+    n, k = a.oom_n, a.oom_k
+    progress(f"generating the CSR matrix {n}x{n}, {a.oom_per_row:g} nonzeros per row")
+    rowptr, col, val = synth.csr_uniform_torch(n, n, a.oom_per_row / n, a.seed, dev)
+    nnz = col.numel()
+    ctx = P.Context(0)
+    csr = P.tsvd_csr_create(ctx, rowptr, col, val, (n, n))
+    g = torch.Generator(device=dev)
+    g.manual_seed(a.seed)
+    v0 = torch.randn((k, n), generator=g, dtype=torch.float64, device=dev)
+    its = [a.oom_iters] * k
+    P.tsvd_sparse(ctx, csr, 1, 0.0, v0[:1], fixed_iters=[2])  # warm-up
+
+    def run(handle, **kw):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        U, S, V, info = P.tsvd_sparse(ctx, handle, k, 0.0, v0, fixed_iters=its, **kw)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        peak = info["workspace_bytes"] + handle.info()["device_bytes"]
+        return ms, peak, info["h2d_bytes"], S.cpu()
+
+    progress("V on the device")
+    ms0, peak0, _, S0 = run(csr)
+    sweep = []
+    for nb in (2, 4, 8, 16):
+        for qs in (1, 2, 4, 8):
+            if qs > nb:
+                continue
+            progress(f"V in pinned host memory: n_b={nb}, q_s={qs}")
+            ms, peak, h2d, S1 = run(csr, factor="host", factor_batches=nb, queue_depth=qs)
+            sweep.append({"n_b": nb, "q_s": qs, "ms": ms, "peak_device_gb": peak / 1e9, "h2d_gb": h2d / 1e9,
+                          "h2d_gbs": h2d / (ms * 1e-3) / 1e9, "bitwise_equal_to_device_V": bool(torch.equal(S0, S1))})
+    progress("tiles and V both in pinned host memory")
+    pin = P.tsvd_csr_create_pinned(ctx, rowptr.cpu().pin_memory(), col.cpu().pin_memory(), val.cpu().pin_memory(),
+                                   (n, n), batch_bytes=256 << 20, queue_depth=2)
+    msp, peakp, h2dp, Sp = run(pin, factor="host", factor_batches=8, queue_depth=2)
+    all_host = {"ms": msp, "peak_device_gb": peakp / 1e9, "h2d_gb": h2dp / 1e9, "h2d_gbs": h2dp / (msp * 1e-3) / 1e9,
+                "tile_batches": pin.info()["batches"], "bitwise_equal_to_device": bool(torch.equal(S0, Sp))}
+    pin.close()
+    csr.close()
+    ctx.close()
+    best = min(sweep, key=lambda r: r["ms"])
+    out = {
+        "metric": METRIC,
+        "value": best["ms"],
+        "unit": "ms (t-SVD, fastest host-V configuration)",
+        "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": best["ms"],
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 values, f64 accumulation and factor", "data": "synthetic",
+        "config": {"workload": f"out-of-memory sweep: sparse CSR {n}x{n}, Poisson({a.oom_per_row:g}) uniform columns "
+                               f"per row ({nnz} nnz), k={k}, {a.oom_iters} fixed iterations per triplet; V (FP64 "
+                               f"{n}x{k}) in pinned host memory, n_b row batches through q_s device buffers",
+                   "n": n, "nnz": nnz, "k": k, "iters": a.oom_iters},
+        "v_on_device": {"ms": ms0, "peak_device_gb": peak0 / 1e9},
+        "sweep": sweep,
+        "tiles_and_v_on_host": all_host,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -641,6 +743,8 @@ def main():
         return stream_main(a)
     if a.workload == "sparse":
         return sparse_main(a)
+    if a.workload == "oom":
+        return oom_main(a)
     import numpy as np
     import torch
 
@@ -815,6 +919,29 @@ def main():
         out["parity_vs_oracle"] = par
         out["meets_1e-6"] = bool(out["meets_1e-6"] and par[a.gram]["meets_1e-6_sigma_1e-4_rad"])
     ctx.close()
+    del A, Utrue, Vtrue, U, S, V
+    torch.cuda.empty_cache()
+    legs = [x for x in a.legs.split(",") if x]
+    if legs:
+        out["legs"] = {}
+    if "serve" in legs:
+        progress("serving leg")
+        sa = argparse.Namespace(**vars(a))
+        sa.window, sa.warm, sa.pool, sa.pool_loc = a.leg_window, 2.0, 24, "host"
+        r = serve_run(sa)
+        out["legs"]["serve"] = {k_: r[k_] for k_ in ("config", "p50_ms", "p99_ms", "max_ms", "requests", "offered_rate",
+                                                      "achieved_rate", "all_ok", "sigma_rel_err_max", "meets_1e-6",
+                                                      "batches", "mean_batch", "batch_phase_ms_mean",
+                                                      "cpu_baseline") if k_ in r}
+        torch.cuda.empty_cache()
+    if "stream" in legs:
+        progress("streaming leg")
+        sa = argparse.Namespace(**vars(a))
+        sa.stream_m = a.leg_stream_m
+        r = stream_run(sa)
+        out["legs"]["stream"] = {k_: r[k_] for k_ in ("config", "value", "unit", "ms_per_step", "roofline",
+                                                       "plain_copy_gbs", "frac_of_plain_copy", "gram_pass_gbs",
+                                                       "overlap", "phase_ms", "h2d_bytes")}
     print(json.dumps(out), flush=True)
     return 0
 

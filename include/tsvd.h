@@ -125,6 +125,11 @@ typedef struct {
   int64_t workspace_bytes; /* device workspace the call used */
   int64_t h2d_bytes;       /* bytes copied host -> device (pinned-host input) */
   double latency_ms;       /* server requests: submission -> completion, host clock; else 0 */
+  double t_stream_copy_ms;    /* pinned-host A, Gram pass: time the copy stream spent copying row batches
+                                 (sum of per-batch HIP event intervals); else 0 */
+  double t_stream_compute_ms; /* the same pass: time the compute stream spent in the batches' Grams */
+  double t_stream_overlap_ms; /* time during which both ran at once (intersection of the two streams'
+                                 per-batch event intervals) */
 } tsvd_info;
 
 typedef struct tsvd_ctx tsvd_ctx;

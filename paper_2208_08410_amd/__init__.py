@@ -156,6 +156,9 @@ class TsvdInfo(ctypes.Structure):
         ("workspace_bytes", ctypes.c_int64),
         ("h2d_bytes", ctypes.c_int64),
         ("latency_ms", ctypes.c_double),
+        ("t_stream_copy_ms", ctypes.c_double),
+        ("t_stream_compute_ms", ctypes.c_double),
+        ("t_stream_overlap_ms", ctypes.c_double),
     ]
 
 
@@ -367,6 +370,9 @@ def _info_dict(info: TsvdInfo, it, lam, k, status):
         "workspace_bytes": info.workspace_bytes,
         "h2d_bytes": info.h2d_bytes,
         "latency_ms": info.latency_ms,
+        "t_stream_copy_ms": info.t_stream_copy_ms,
+        "t_stream_compute_ms": info.t_stream_compute_ms,
+        "t_stream_overlap_ms": info.t_stream_overlap_ms,
     }
 
 

@@ -395,6 +395,9 @@ void fill_info(tsvd_info* info, const PhaseResult& pr, int k, bool right, tsvd_c
   info->workspace_bytes = (int64_t)need;
   info->h2d_bytes = h2d;
   info->latency_ms = 0;
+  info->t_stream_copy_ms = 0;
+  info->t_stream_compute_ms = 0;
+  info->t_stream_overlap_ms = 0;
 }
 
 tsvd_status not_converged(tsvd_ctx* ctx, const PhaseResult& pr, const tsvd_opts* o) {
@@ -436,6 +439,9 @@ tsvd_status tsvd_power_gram(tsvd_ctx* ctx, void* B, int32_t dtype, int64_t d, in
     info->rank_deficient = pr.rankdef;
     info->branch_right = 1;
     info->latency_ms = 0;
+    info->t_stream_copy_ms = 0;
+    info->t_stream_compute_ms = 0;
+    info->t_stream_overlap_ms = 0;
     info->workspace_bytes = (int64_t)need;
     if (info->iters) memcpy(info->iters, pr.iters.data(), (size_t)k * 4);
     if (info->lambda) memcpy(info->lambda, pr.lams.data(), (size_t)k * 8);
@@ -706,23 +712,46 @@ tsvd_status dense_pinned(tsvd_ctx* ctx, const float* A, int64_t m, int64_t n, in
     return 0;
   };
 
-  hipEventRecord(ctx->ev[0], s);
-  if (hipStreamWaitEvent(cs, ctx->ev[0], 0) != hipSuccess) { cleanup(); return fail(ctx, TSVD_ERR_HIP, "wait"); }
-  if (zero_cols_launch(U, ldu, m, k, s) || zero_cols_launch(V, ldv, n, k, s) || zero_cols_launch(S, k, k, 1, s)) {
+  // per-batch timing of the Gram pass (copy and compute intervals on their
+  // streams), when the caller asks for info
+  std::vector<hipEvent_t> tev;
+  if (info) {
+    tev.resize((size_t)nbatch * 4, nullptr);
+    for (auto& e : tev)
+      if (hipEventCreate(&e) != hipSuccess) {
+        for (auto& f : tev)
+          if (f) (void)hipEventDestroy(f);
+        cleanup();
+        return fail(ctx, TSVD_ERR_HIP, "timing events");
+      }
+  }
+  auto cleanup_all = [&]() {
+    for (auto& f : tev) (void)hipEventDestroy(f);
+    tev.clear();
     cleanup();
+  };
+  hipEventRecord(ctx->ev[0], s);
+  if (hipStreamWaitEvent(cs, ctx->ev[0], 0) != hipSuccess) { cleanup_all(); return fail(ctx, TSVD_ERR_HIP, "wait"); }
+  if (zero_cols_launch(U, ldu, m, k, s) || zero_cols_launch(V, ldv, n, k, s) || zero_cols_launch(S, k, k, 1, s)) {
+    cleanup_all();
     return fail(ctx, TSVD_ERR_HIP, "clear outputs");
   }
   // ---- pass 1: B = sum_b A_b^T A_b
   for (int64_t b = 0; b < nbatch && !rc; b++) {
     const int slot = (int)(b % Q);
-    if ((rc = copy_batch(b, slot, b >= Q))) break;
+    if (b >= Q && hipStreamWaitEvent(cs, consumed[slot], 0) != hipSuccess) { rc = TSVD_ERR_HIP; break; }
+    if (!tev.empty() && hipEventRecord(tev[4 * b], cs) != hipSuccess) { rc = TSVD_ERR_HIP; break; }
+    if ((rc = copy_batch(b, slot, false))) break;
+    if (!tev.empty() && hipEventRecord(tev[4 * b + 1], cs) != hipSuccess) { rc = TSVD_ERR_HIP; break; }
     if (hipStreamWaitEvent(s, copied[slot], 0) != hipSuccess) { rc = TSVD_ERR_HIP; break; }
     const int64_t rows = (b == nbatch - 1) ? last_rows : R;
     const SyrkPlan& sp = (b == nbatch - 1) ? sp_last : sp_full;
+    if (!tev.empty() && hipEventRecord(tev[4 * b + 2], s) != hipSuccess) { rc = TSVD_ERR_HIP; break; }
     if ((rc = syrk_launch(mode, 0, buf[slot], rows, n, n, sp, partial, B, ldb, b > 0 ? 1 : 0, s))) break;
+    if (!tev.empty() && hipEventRecord(tev[4 * b + 3], s) != hipSuccess) { rc = TSVD_ERR_HIP; break; }
     if (hipEventRecord(consumed[slot], s) != hipSuccess) { rc = TSVD_ERR_HIP; break; }
   }
-  if (rc) { cleanup(); return from_internal(ctx, rc, "pinned Gram pass"); }
+  if (rc) { cleanup_all(); return from_internal(ctx, rc, "pinned Gram pass"); }
   hipEventRecord(ctx->ev[1], s);
   // ---- prefetch the first batches of pass 2 while the power iteration runs
   const int64_t pre = nbatch < Q ? nbatch : Q;
@@ -732,7 +761,7 @@ tsvd_status dense_pinned(tsvd_ctx* ctx, const float* A, int64_t m, int64_t n, in
   st = power_phase(ctx, bump, onchip, pp, B, 0, d, ldb, k, o, V, ldv, &pr, s);
   if (st) {
     (void)hipStreamSynchronize(cs);
-    cleanup();
+    cleanup_all();
     return st;
   }
   hipEventRecord(ctx->ev[2], s);
@@ -753,9 +782,29 @@ tsvd_status dense_pinned(tsvd_ctx* ctx, const float* A, int64_t m, int64_t n, in
   if (!rc && kd > 0) rc = finish_scale_sign_launch(U, ldu, m, S, V, ldv, n, U, ldu, m, kd, 1, ssq + tiles_total * k, s);
   hipEventRecord(ctx->ev[3], s);
   if (!rc && (hipStreamSynchronize(s) != hipSuccess || hipStreamSynchronize(cs) != hipSuccess)) rc = TSVD_ERR_HIP;
-  cleanup();
+  double copy_ms = 0.0, comp_ms = 0.0, overlap_ms = 0.0;
+  if (!rc && !tev.empty()) {
+    // intervals relative to ev[0]; each stream's intervals are disjoint and in order
+    std::vector<float> t(tev.size());
+    for (size_t i = 0; i < tev.size(); i++) hipEventElapsedTime(&t[i], ctx->ev[0], tev[i]);
+    size_t j = 0;
+    for (int64_t b = 0; b < nbatch; b++) {
+      const double c0 = t[4 * b], c1 = t[4 * b + 1];
+      copy_ms += c1 - c0;
+      comp_ms += t[4 * b + 3] - t[4 * b + 2];
+      while (j < (size_t)nbatch && t[4 * j + 3] <= c0) j++;
+      for (size_t q = j; q < (size_t)nbatch && t[4 * q + 2] < c1; q++)
+        overlap_ms += std::max(0.0, std::min(c1, (double)t[4 * q + 3]) - std::max(c0, (double)t[4 * q + 2]));
+    }
+  }
+  cleanup_all();
   if (rc) return from_internal(ctx, rc, "pinned finish pass");
   fill_info(info, pr, k, true, ctx, need, (int64_t)(m * n * 4) * (kd > 0 ? 2 : 1));
+  if (info) {
+    info->t_stream_copy_ms = copy_ms;
+    info->t_stream_compute_ms = comp_ms;
+    info->t_stream_overlap_ms = overlap_ms;
+  }
   return not_converged(ctx, pr, o);
 }
 

@@ -342,6 +342,9 @@ tsvd_status batch_problem_result(const BatchPlan& bp, const tsvd_problem& q, int
     if (info->lambda) memcpy(info->lambda, &bp.hl[ko], (size_t)p.k * 8);
     info->h2d_bytes = 0;
     info->latency_ms = 0;
+    info->t_stream_copy_ms = 0;
+    info->t_stream_compute_ms = 0;
+    info->t_stream_overlap_ms = 0;
   }
   return si;
 }

@@ -635,6 +635,9 @@ tsvd_status tsvd_sparse(tsvd_ctx* ctx, const tsvd_csr* cc, const tsvd_opts* o, d
     info->workspace_bytes = (int64_t)need;
     info->h2d_bytes = op.h2d_bytes() + fac.h2d_bytes();
     info->latency_ms = 0;
+    info->t_stream_copy_ms = 0;
+    info->t_stream_compute_ms = 0;
+    info->t_stream_overlap_ms = 0;
   }
   if (!r.all_conv && !o->fixed_iters && o->eps > 0)
     return fail(ctx, TSVD_ERR_NOT_CONVERGED, "some triplet reached max_iter");

@@ -83,6 +83,7 @@ int main(void) {
   F(tsvd_tuning, group_kchunk) F(tsvd_tuning, sparse_row_bits) F(tsvd_tuning, sparse_col_bits) F(tsvd_tuning, power_path)
   Z(tsvd_tuning)
   F(tsvd_info, k_done) F(tsvd_info, iters) F(tsvd_info, lambda) F(tsvd_info, t_gram_ms) F(tsvd_info, h2d_bytes) F(tsvd_info, latency_ms)
+  F(tsvd_info, t_stream_copy_ms) F(tsvd_info, t_stream_compute_ms) F(tsvd_info, t_stream_overlap_ms)
   Z(tsvd_info)
   F(tsvd_problem, A) F(tsvd_problem, dtype) F(tsvd_problem, m) F(tsvd_problem, lda) F(tsvd_problem, opts)
   F(tsvd_problem, U) F(tsvd_problem, ldu) F(tsvd_problem, S) F(tsvd_problem, V) F(tsvd_problem, ldv)

@@ -65,3 +65,21 @@ def test_pinned_rejects_pageable_and_left_branch(ctx):
     with pytest.raises(P.TsvdError) as e:
         P.tsvd_dense(ctx, Aw, 2, 1e-8, to_dev(synth.start_vectors(2, 50, seed=1)))
     assert e.value.status == P.UNSUPPORTED
+
+
+def test_pinned_stream_timing_is_consistent(ctx):
+    """The Gram pass reports its copy and compute busy times and their overlap
+    from per-batch HIP events: each is positive, the overlap fits inside both,
+    with 12 batches through two buffers some copy runs beside a Gram, and the
+    pass cannot be shorter than the busy time of either stream."""
+    m, n, k = 48000, 1024, 2
+    dk = synth.dense_known(m, n, synth.spectrum_geometric(0.9, n), seed=5, dtype=np.float32)
+    st = to_dev(synth.start_vectors(k, n, seed=6))
+    U, S, V, info = P.tsvd_dense(ctx, pinned(dk.A), k, 1e-6, st, rows_per_block=4000, queue_depth=2)
+    c, g, o = info["t_stream_copy_ms"], info["t_stream_compute_ms"], info["t_stream_overlap_ms"]
+    assert c > 0 and g > 0 and o > 0
+    assert o <= min(c, g) + 1e-3
+    assert info["t_gram_ms"] >= max(c, g) - 1e-3
+    # the in-HBM path has no streamed pass
+    _, _, _, infd = P.tsvd_dense(ctx, to_dev(dk.A), k, 1e-6, st)
+    assert infd["t_stream_copy_ms"] == 0 and infd["t_stream_overlap_ms"] == 0
