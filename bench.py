@@ -82,6 +82,7 @@ def parse():
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serve: server device budget")
     ap.add_argument("--team-kib", type=int, default=0, help="serve: batched power team size rule (0 = library)")
     ap.add_argument("--max-batch", type=int, default=0, help="serve: requests per batch launch at most (0 = all)")
+    ap.add_argument("--lanes", type=int, default=0, help="serve: batches on the device at once (0 = library)")
     ap.add_argument("--batch-size", type=int, default=64, help="batch: problems per tsvd_dense_batched call")
     ap.add_argument("--pool-gen", default="gpu", choices=["gpu", "cpu"],
                     help="serve/batch: build the matrices on the GPU or on the host (then copy)")
@@ -377,7 +378,7 @@ def serve_run(a):
     ctx = P.Context(0)
     if a.team_kib:
         P.set_tuning(ctx, team_kib=a.team_kib)
-    srv = P.Server(ctx, hbm_budget=int(a.budget_gb * (1 << 30)), max_batch=a.max_batch)
+    srv = P.Server(ctx, hbm_budget=int(a.budget_gb * (1 << 30)), max_batch=a.max_batch, lanes=a.lanes)
     tickets = []
     progress(f"serving {len(arrivals)} arrivals")
     t_start = time.perf_counter()
@@ -428,7 +429,7 @@ def serve_run(a):
                                f"pool of {a.pool} matrices in {'pinned host memory' if a.pool_loc == 'host' else 'HBM'}"
                                f", eps={eps}", "rate": a.rate, "window_s": a.window, "pool": a.pool,
                    "pool_loc": a.pool_loc, "budget_gb": a.budget_gb, "team_kib": a.team_kib,
-                   "max_batch": a.max_batch},
+                   "max_batch": a.max_batch, "lanes": a.lanes},
         "p50_ms": float(np.percentile(lat, 50)),
         "p99_ms": float(np.percentile(lat, 99)),
         "max_ms": float(lat.max()),
@@ -443,6 +444,8 @@ def serve_run(a):
         "meets_1e-6": bool(errs.max() < 1e-6),
         "batches": st["batches"],
         "mean_batch": st["mean_batch"],
+        "lanes_busy_max": st["lanes_busy_max"],
+        "overlapped_launches": st["overlapped"],
         "batch_phase_ms_mean": _batch_phases(results),
         "peak_bytes": st["peak_bytes"],
         "gen_seconds": gen_s,
@@ -931,7 +934,8 @@ def main():
         r = serve_run(sa)
         out["legs"]["serve"] = {k_: r[k_] for k_ in ("config", "p50_ms", "p99_ms", "max_ms", "requests", "offered_rate",
                                                       "achieved_rate", "all_ok", "sigma_rel_err_max", "meets_1e-6",
-                                                      "batches", "mean_batch", "batch_phase_ms_mean",
+                                                      "batches", "mean_batch", "lanes_busy_max",
+                                                      "overlapped_launches", "batch_phase_ms_mean",
                                                       "cpu_baseline") if k_ in r}
         torch.cuda.empty_cache()
     if "stream" in legs:

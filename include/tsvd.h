@@ -154,7 +154,8 @@ const char* tsvd_last_error(const tsvd_ctx* ctx);
 typedef struct {
   int32_t gram_tile;     /* BF16X3 Gram tile edge: 0 (library choice), 128 or 256 */
   int32_t gram_chunks;   /* contraction chunks (split-K) per Gram launch: 0 = library choice */
-  int32_t power_blocks;  /* workgroups of the power-iteration launch: 0 = one per CU */
+  int32_t power_blocks;  /* workgroups of the power-iteration launch: 0 = one per CU; for batches the cap
+                            on every team and on the power launch's grid */
   int32_t team_kib;      /* batched power launch: KiB of a problem's Gram per team workgroup, which
                             sets the team size (ceil(4 d^2 / (team_kib * 1024)) workgroups);
                             0 = 256; range [8, 65536] */
@@ -287,6 +288,10 @@ typedef struct {
                               tables; the rest holds admitted requests' workspaces and staged A */
   int32_t max_slots;       /* requests admitted and not yet completed, at most; 0 = 256 */
   int32_t max_batch;       /* requests per batch launch, at most; 0 = max_slots */
+  int32_t lanes;           /* batches that may run on the device at once, 1..8; 0 = 2.  Each batch's
+                              power launch and every request's team are capped at (CUs / lanes)
+                              workgroups, so the persistent launches of all lanes always fit on the
+                              chip together */
 } tsvd_server_config;
 
 typedef struct {
@@ -298,21 +303,24 @@ typedef struct {
   int64_t peak_bytes;      /* high-water mark of admitted request footprints */
   int64_t in_flight;       /* admitted or running now */
   int64_t waiting;         /* submitted, not yet admitted */
+  int64_t lanes_busy_max;  /* most batches on the device at once so far */
+  int64_t overlapped;      /* batch launches made while another batch was on the device */
 } tsvd_server_stats;
 
 /* Start a server on ctx's device: one device allocation of cfg->hbm_budget
- * bytes, two internal streams (compute, host->device copies) and a worker
+ * bytes, a compute stream per lane, a host->device copy stream and a worker
  * thread.  The worker owns ctx until tsvd_server_destroy: make no other call
  * on ctx meanwhile.  Each worker cycle admits waiting requests in arrival
  * order while a slot is free and the budget covers the request's footprint
  * (its Gram, split-K partials and finish sums, plus its A when A is in pinned
- * host memory, which is then copied at once on the copy stream); when the
- * device is idle it launches every admitted request as one batch (as
- * tsvd_dense_batched); when that batch completes it frees its memory and
- * completes its tickets.  Requests arriving while a batch runs are admitted
- * and copied during it and form the next batch.  A request's result is the
- * same whether it runs alone or in any mix (its launch shapes depend on it
- * alone). */
+ * host memory, which is then copied at once on the copy stream); whenever a
+ * lane is idle it launches the admitted requests on it as one batch (as
+ * tsvd_dense_batched, with teams of at most CUs / lanes workgroups); when a
+ * lane's batch completes it frees that batch's memory and completes its
+ * tickets.  So a request that arrives while another batch runs starts on a
+ * free lane at once and its work overlaps the running batch on the device.  A
+ * request's result is the same whether it runs alone or in any mix (its
+ * launch shapes depend on it and the lane count alone). */
 tsvd_status tsvd_server_create(tsvd_ctx* ctx, const tsvd_server_config* cfg, tsvd_server** out);
 
 /* Queue one request; returns at once with a ticket.  The problem struct is

@@ -120,6 +120,7 @@ class TsvdServerConfig(ctypes.Structure):
         ("hbm_budget", ctypes.c_int64),
         ("max_slots", ctypes.c_int32),
         ("max_batch", ctypes.c_int32),
+        ("lanes", ctypes.c_int32),
     ]
 
 
@@ -138,6 +139,8 @@ class TsvdServerStats(ctypes.Structure):
         ("peak_bytes", ctypes.c_int64),
         ("in_flight", ctypes.c_int64),
         ("waiting", ctypes.c_int64),
+        ("lanes_busy_max", ctypes.c_int64),
+        ("overlapped", ctypes.c_int64),
     ]
 
 
@@ -567,9 +570,9 @@ class Server:
     (U, S, V, info) once the request completed (info["status"] holds its
     status)."""
 
-    def __init__(self, ctx: Context, hbm_budget: int, max_slots: int = 0, max_batch: int = 0):
+    def __init__(self, ctx: Context, hbm_budget: int, max_slots: int = 0, max_batch: int = 0, lanes: int = 0):
         self.ctx = ctx
-        cfg = TsvdServerConfig(int(hbm_budget), int(max_slots), int(max_batch))
+        cfg = TsvdServerConfig(int(hbm_budget), int(max_slots), int(max_batch), int(lanes))
         h = ctypes.c_void_p()
         ctx.check(ctx.lib.tsvd_server_create(ctx.handle, ctypes.byref(cfg), ctypes.byref(h)))
         self.handle = h

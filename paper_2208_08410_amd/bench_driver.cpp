@@ -16,6 +16,11 @@
 //     workgroup publishes its rows of a d-vector and two partial sums, then
 //     gathers all of them), one workgroup per CU, no products: the latency
 //     floor of one power iteration
+//   tsvd_bench gather
+//     random 4-byte gathers x[idx[i]] (idx uniform over a set of 2^k floats,
+//     2^26 gathers, eight in flight per lane) for gathered sets from 1 MiB to
+//     1 GiB: the gather ceiling of the sparse products once x leaves an XCD's
+//     L2
 //   tsvd_bench batch COUNT [steps warmup seed team_kib]
 //     COUNT problems of the serving mix (m log-uniform in [1024, 65536], n in
 //     [128, 4096], k in {8, 16, 32, 64}, s_i = 0.95^i, eps = 5e-8) solved by
@@ -212,6 +217,67 @@ static int run_exchange(int d, int rounds) {
   return 0;
 }
 
+// sum of x[idx[i]] over a grid-stride range, 8 independent gathers per lane
+__global__ __launch_bounds__(256) void gather_kernel(const float* __restrict__ x, const uint32_t* __restrict__ idx,
+                                                     size_t n, float* out) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  float acc = 0.f;
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + 7 * stride < n; i += 8 * stride) {
+    uint32_t j[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) j[u] = __builtin_nontemporal_load(idx + i + u * stride);
+#pragma unroll
+    for (int u = 0; u < 8; u++) acc += x[j[u]];
+  }
+  for (; i < n; i += stride) acc += x[idx[i]];
+  if (acc == 12345.f) out[0] = acc;  // keeps the loads
+}
+
+static int run_gather() {
+  const size_t n = (size_t)1 << 26;
+  const int max_bits = 28;  // 2^28 floats = 1 GiB
+  std::vector<uint32_t> hidx(n);
+  float *x = nullptr, *out = nullptr;
+  uint32_t* idx = nullptr;
+  if (hipMalloc(&x, ((size_t)1 << max_bits) * 4) || hipMalloc(&idx, n * 4) || hipMalloc(&out, 64)) {
+    fprintf(stderr, "device alloc\n");
+    return 1;
+  }
+  (void)hipMemset(x, 0, ((size_t)1 << max_bits) * 4);
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  printf("{\"gathers\": %zu, \"sets\": [", n);
+  bool first = true;
+  for (int bits = 18; bits <= max_bits; bits += 2) {
+    const uint32_t mask = (1u << bits) - 1u;
+    for (size_t i = 0; i < n; i++) hidx[i] = (uint32_t)(splitmix(((uint64_t)bits << 40) + i) & mask);  // < 2^bits
+    (void)hipMemcpy(idx, hidx.data(), n * 4, hipMemcpyHostToDevice);
+    const int grid = 256 * 32;
+    hipLaunchKernelGGL(gather_kernel, dim3(grid), dim3(256), 0, 0, x, idx, n, out);
+    float best = 1e30f;
+    for (int r = 0; r < 5; r++) {
+      (void)hipEventRecord(e0, 0);
+      hipLaunchKernelGGL(gather_kernel, dim3(grid), dim3(256), 0, 0, x, idx, n, out);
+      (void)hipEventRecord(e1, 0);
+      (void)hipEventSynchronize(e1);
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      best = fminf(best, ms);
+    }
+    printf("%s{\"set_mib\": %.0f, \"ms\": %.4f, \"g_gathers_per_s\": %.1f}", first ? "" : ", ",
+           ((size_t)1 << bits) * 4.0 / (1 << 20), best, n / (best * 1e-3) / 1e9);
+    first = false;
+  }
+  printf("]}\n");
+  fflush(stdout);
+  (void)hipFree(x);
+  (void)hipFree(idx);
+  (void)hipFree(out);
+  return 0;
+}
+
 static int run_copy(size_t bytes, int reps) {
   if (bytes == 0 || bytes % 16) { fprintf(stderr, "copy: BYTES must be a positive multiple of 16\n"); return 2; }
   void *a, *b;
@@ -372,6 +438,7 @@ int main(int argc, char** argv) {
   if (argc > 1 && argv[1][0] == 'b')
     return run_batch(argc > 2 ? atoi(argv[2]) : 64, argc > 3 ? atoi(argv[3]) : 3, argc > 4 ? atoi(argv[4]) : 1,
                      argc > 5 ? strtoull(argv[5], nullptr, 10) : 7, argc > 6 ? atoi(argv[6]) : 0);
+  if (argc > 1 && argv[1][0] == 'g') return run_gather();
   if (argc > 1 && argv[1][0] == 'c')
     return run_copy(argc > 2 ? strtoull(argv[2], nullptr, 10) : ((size_t)1 << 30), argc > 3 ? atoi(argv[3]) : 5);
   const int64_t m = argc > 1 ? atoll(argv[1]) : 200000;

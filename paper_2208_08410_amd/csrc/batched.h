@@ -53,8 +53,9 @@ struct BatchPlan {
                                      align256(total_k * 8); }
 };
 
-// validate the problems and plan tiles, teams and workspace sizes
-tsvd_status batch_plan(tsvd_ctx* ctx, int count, const tsvd_problem* probs, BatchPlan& bp);
+// validate the problems and plan tiles, teams and workspace sizes; team_cap
+// (0 = the CU count) bounds every team and the power launch's grid
+tsvd_status batch_plan(tsvd_ctx* ctx, int count, const tsvd_problem* probs, BatchPlan& bp, int team_cap = 0);
 // enqueue the whole batch on `stream` (asynchronous).  bbase: batch workspace
 // (bp.batch_ws_bytes); pbase[i]: problem i's workspace (bp.P[i].ws_bytes).
 // ev (optional, 4 events) marks start / after Gram / after power / end.

@@ -49,7 +49,8 @@ double team_cost(int64_t d, int k, int g) { return (double)k * std::max((double)
 
 }  // namespace
 
-tsvd_status batch_plan(tsvd_ctx* ctx, int count, const tsvd_problem* probs, BatchPlan& bp) {
+tsvd_status batch_plan(tsvd_ctx* ctx, int count, const tsvd_problem* probs, BatchPlan& bp, int team_cap) {
+  const int cap = team_cap > 0 ? std::min(team_cap, ctx->num_cu) : ctx->num_cu;
   // default: 256 KiB of the problem's Gram per member, about what a member
   // holds on chip (LDS rows plus register rows) up to a dimension of 8192
   const int team_kib = ctx->tuning.team_kib > 0 ? ctx->tuning.team_kib : 256;
@@ -97,7 +98,7 @@ tsvd_status batch_plan(tsvd_ctx* ctx, int count, const tsvd_problem* probs, Batc
     p.kchunk = kchunk;
     const int64_t M = p.right ? q.m : q.n;
     p.nb = (int)((M + 127) / 128);
-    p.G = wanted_team(p.d, ctx->num_cu, team_kib);
+    p.G = wanted_team(p.d, cap, team_kib);
     // the batched kernel's own static LDS comes out of the per-workgroup budget
     if (power_plan(4, (int)p.d, p.k, ctx->num_cu, ctx->max_lds - power_dyn_static_lds(), p.G, &p.pp))
       return fail(ctx, TSVD_ERR_UNSUPPORTED, "problem %d: d=%lld too large for the LDS-resident iterate", i,
@@ -119,7 +120,7 @@ tsvd_status batch_plan(tsvd_ctx* ctx, int count, const tsvd_problem* probs, Batc
   });
   int64_t seats = 0;
   for (auto& p : bp.P) seats += p.G;
-  bp.grid = (int)std::min<int64_t>(seats, ctx->num_cu);
+  bp.grid = (int)std::min<int64_t>(seats, cap);
 
   // batch-level workspace: descriptors, statuses and iteration logs, then the
   // cleared region (queue counters and every problem's exchange buffers)
@@ -364,7 +365,7 @@ tsvd_status tsvd_dense_batched(tsvd_ctx* ctx, int32_t count, const tsvd_problem*
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, TSVD_ERR_HIP, "hipSetDevice");
   hipStream_t stream = (hipStream_t)stream_;
   BatchPlan bp;
-  tsvd_status st = batch_plan(ctx, count, probs, bp);
+  tsvd_status st = batch_plan(ctx, count, probs, bp, ctx->tuning.power_blocks);
   if (st) return st;
   size_t need = bp.batch_ws_bytes;
   std::vector<size_t> poff(count);

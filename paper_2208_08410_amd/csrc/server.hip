@@ -5,15 +5,21 @@
 //      covers their footprint (Gram, split-K partials, finish sums and the
 //      staged copy of a host-resident A) and a slot is free; host-resident A is
 //      copied on the copy stream at once;
-//   2. when no batch is on the device, launches every admitted request as one
-//      batch (grouped Gram, team power kernel, grouped finish) on the compute
-//      stream, after the copies of its inputs;
-//   3. when the batch's completion event has fired, releases its memory and
-//      completes its tickets (latency = completion - submission, host clock).
-// Requests that arrive while a batch runs are admitted and copied during it
-// and form the next batch, so the device is never idle while work waits.
-// Each request's result is independent of the batch it ran in (team sizes and
-// Gram chunking depend on the request alone).
+//   2. launches the admitted requests as one batch (grouped Gram, team power
+//      kernel, grouped finish) on any idle lane: each lane is a compute stream,
+//      and up to `lanes` batches run on the device at once;
+//   3. when a lane's completion event has fired, releases that batch's memory
+//      and completes its tickets (latency = completion - submission, host
+//      clock).
+// A request that arrives while a batch runs therefore starts on a free lane
+// at once, and its Gram, power steps and finish overlap the running batch.
+// Every team (and every batch's power launch) is capped at CUs / lanes
+// workgroups, so the persistent power launches of all lanes together never
+// need more CUs than the chip has: each launch's workgroups all become
+// resident once the other lanes' short Gram and finish kernels drain, and no
+// lane waits on another.  Each request's result is independent of the batch
+// and the lane it ran in (team sizes and Gram chunking depend on the request
+// and the lane count alone).
 #include <math.h>
 #include <string.h>
 
@@ -116,15 +122,28 @@ struct Request {
 
 using namespace tsvd;
 
+struct Lane {
+  hipStream_t compute = nullptr;
+  hipEvent_t done = nullptr;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  std::vector<uint64_t> running;
+  tsvd::BatchPlan plan;
+  std::vector<tsvd_problem> run_probs;
+  char* batch_ws = nullptr;
+  bool active = false;
+  char* hpin = nullptr;  // pinned host staging of the batch's descriptors and results
+  size_t hpin_bytes = 0;
+};
+
 struct tsvd_server {
   tsvd_ctx* ctx = nullptr;
   tsvd_server_config cfg = {};
-  hipStream_t compute = nullptr, copy = nullptr;
-  hipEvent_t batch_done = nullptr;
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipStream_t copy = nullptr;
+  std::vector<Lane> lanes;
+  int team_cap = 0;  // CUs / lanes
   char* pool = nullptr;
   Arena arena;    // request workspaces and staged copies of host A
-  Arena tables;   // the running batch's tables and team buffers
+  Arena tables;   // the running batches' tables and team buffers
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   bool stop = false;
@@ -134,19 +153,17 @@ struct tsvd_server {
   std::unordered_map<uint64_t, Request*> reqs;     // every ticket not yet collected
   std::vector<uint64_t> admitted;                  // admitted, not yet launched
   int in_flight = 0;                               // admitted + running
-  // the batch on the device
-  std::vector<uint64_t> running;
-  BatchPlan plan;
-  std::vector<tsvd_problem> run_probs;
-  char* batch_ws = nullptr;
-  bool batch_active = false;
-  char* hpin = nullptr;  // pinned host staging of the batch's descriptors and results
-  size_t hpin_bytes = 0;
   // statistics
   int64_t submitted = 0, completed = 0, failed = 0, rejected = 0, batches = 0, batched_problems = 0;
-  int64_t peak_bytes = 0;
+  int64_t peak_bytes = 0, lanes_busy_max = 0, overlapped = 0;
   std::vector<double> latencies_ms;
   std::string error;
+
+  int busy_lanes() const {
+    int b = 0;
+    for (const Lane& l : lanes) b += l.active ? 1 : 0;
+    return b;
+  }
 };
 
 namespace {
@@ -187,7 +204,7 @@ void admit(tsvd_server* s) {
   while (!s->waiting.empty() && s->in_flight < s->cfg.max_slots) {
     Request* r = s->reqs[s->waiting.front()];
     BatchPlan one;
-    tsvd_status st = batch_plan(s->ctx, 1, &r->prob, one);
+    tsvd_status st = batch_plan(s->ctx, 1, &r->prob, one, s->team_cap);
     if (st != TSVD_OK) {  // arguments were checked at submit; planning limits remain
       s->waiting.pop_front();
       finish_request(s, r, st);
@@ -235,16 +252,23 @@ void admit(tsvd_server* s) {
   }
 }
 
-// step 2: launch the admitted requests as one batch (lock held)
+// step 2: launch the admitted requests as one batch on an idle lane (lock held)
 void launch(tsvd_server* s) {
-  if (s->batch_active || s->admitted.empty()) return;
+  if (s->admitted.empty()) return;
+  Lane* L = nullptr;
+  for (Lane& l : s->lanes)
+    if (!l.active) {
+      L = &l;
+      break;
+    }
+  if (!L) return;
   const int maxb = s->cfg.max_batch;
   std::vector<uint64_t> take;
   for (size_t i = 0; i < s->admitted.size() && (int)take.size() < maxb; i++) take.push_back(s->admitted[i]);
   while (!take.empty()) {
-    s->run_probs.clear();
-    for (uint64_t t : take) s->run_probs.push_back(s->reqs[t]->prob);
-    tsvd_status st = batch_plan(s->ctx, (int)take.size(), s->run_probs.data(), s->plan);
+    L->run_probs.clear();
+    for (uint64_t t : take) L->run_probs.push_back(s->reqs[t]->prob);
+    tsvd_status st = batch_plan(s->ctx, (int)take.size(), L->run_probs.data(), L->plan, s->team_cap);
     if (st != TSVD_OK) {
       for (uint64_t t : take) {
         Request* r = s->reqs[t];
@@ -255,88 +279,92 @@ void launch(tsvd_server* s) {
       s->cv_done.notify_all();
       return;
     }
-    s->batch_ws = s->tables.alloc(s->plan.batch_ws_bytes);
-    if (s->batch_ws) break;
-    take.pop_back();  // tables too large for their region: a smaller batch
+    L->batch_ws = s->tables.alloc(L->plan.batch_ws_bytes);
+    if (L->batch_ws) break;
+    take.pop_back();  // tables too large for the free part of their region: a smaller batch
   }
   if (take.empty()) return;
-  if (s->hpin_bytes < s->plan.host_bytes()) {  // no batch runs now: the old area is free
-    if (s->hpin) (void)hipHostFree(s->hpin);
-    s->hpin = nullptr;
-    s->hpin_bytes = 0;
-    const size_t want = 2 * s->plan.host_bytes();
-    if (hipHostMalloc((void**)&s->hpin, want, hipHostMallocDefault) != hipSuccess) {
+  if (L->hpin_bytes < L->plan.host_bytes()) {  // the lane is idle: its old area is free
+    if (L->hpin) (void)hipHostFree(L->hpin);
+    L->hpin = nullptr;
+    L->hpin_bytes = 0;
+    const size_t want = 2 * L->plan.host_bytes();
+    if (hipHostMalloc((void**)&L->hpin, want, hipHostMallocDefault) != hipSuccess) {
       (void)hipGetLastError();
-      s->hpin = nullptr;
+      L->hpin = nullptr;
     } else {
-      s->hpin_bytes = want;
+      L->hpin_bytes = want;
     }
   }
   s->admitted.erase(s->admitted.begin(), s->admitted.begin() + take.size());
   std::vector<char*> pbase;
   for (uint64_t t : take) {
     Request* r = s->reqs[t];
-    if (r->copied) (void)hipStreamWaitEvent(s->compute, r->copied, 0);
+    if (r->copied) (void)hipStreamWaitEvent(L->compute, r->copied, 0);
     pbase.push_back(r->ws);
     r->state = RUNNING;
   }
   tsvd_status st =
-      batch_enqueue(s->ctx, s->run_probs.data(), s->plan, s->batch_ws, pbase.data(), s->compute, s->ev, s->hpin);
-  if (st == TSVD_OK && hipEventRecord(s->batch_done, s->compute) != hipSuccess) st = TSVD_ERR_HIP;
+      batch_enqueue(s->ctx, L->run_probs.data(), L->plan, L->batch_ws, pbase.data(), L->compute, L->ev, L->hpin);
+  if (st == TSVD_OK && hipEventRecord(L->done, L->compute) != hipSuccess) st = TSVD_ERR_HIP;
   if (st != TSVD_OK) {
     s->error = s->ctx->last_error;
-    (void)hipStreamSynchronize(s->compute);
+    (void)hipStreamSynchronize(L->compute);
     for (uint64_t t : take) {
       Request* r = s->reqs[t];
       release_request(s, r);
       finish_request(s, r, st);
     }
-    s->tables.release(s->batch_ws);
-    s->batch_ws = nullptr;
+    s->tables.release(L->batch_ws);
+    L->batch_ws = nullptr;
     s->cv_done.notify_all();
     return;
   }
-  s->running = take;
-  s->batch_active = true;
+  if (s->busy_lanes() > 0) s->overlapped++;
+  L->running = take;
+  L->active = true;
+  s->lanes_busy_max = std::max<int64_t>(s->lanes_busy_max, s->busy_lanes());
   s->batches++;
   s->batched_problems += (int64_t)take.size();
 }
 
-// step 3: collect a finished batch (lock held)
+// step 3: collect the finished batches (lock held)
 void collect(tsvd_server* s) {
-  if (!s->batch_active) return;
-  const hipError_t q = hipEventQuery(s->batch_done);
-  if (q == hipErrorNotReady) return;
-  for (size_t i = 0; i < s->running.size(); i++) {
-    Request* r = s->reqs[s->running[i]];
-    tsvd_status st = TSVD_ERR_HIP;
-    if (q == hipSuccess) {
-      r->info.iters = r->iters.data();
-      r->info.lambda = r->lambda.data();
-      st = batch_problem_result(s->plan, s->run_probs[i], (int)i, &r->info);
-      float tg = 0, te = 0, tf = 0, tt = 0;
-      (void)hipEventElapsedTime(&tg, s->ev[0], s->ev[1]);
-      (void)hipEventElapsedTime(&te, s->ev[1], s->ev[2]);
-      (void)hipEventElapsedTime(&tf, s->ev[2], s->ev[3]);
-      (void)hipEventElapsedTime(&tt, s->ev[0], s->ev[3]);
-      r->info.t_gram_ms = tg;
-      r->info.t_eig_ms = te;
-      r->info.t_final_ms = tf;
-      r->info.t_total_ms = tt;
-      r->info.workspace_bytes = (int64_t)r->footprint;
-      r->info.h2d_bytes = r->loc == TSVD_LOC_PINNED_HOST ? (int64_t)(r->prob.m * r->prob.lda * 4) : 0;
-    } else {
-      s->error = std::string("batch completion: ") + hipGetErrorString(q);
-      (void)hipGetLastError();
+  for (Lane& L : s->lanes) {
+    if (!L.active) continue;
+    const hipError_t q = hipEventQuery(L.done);
+    if (q == hipErrorNotReady) continue;
+    for (size_t i = 0; i < L.running.size(); i++) {
+      Request* r = s->reqs[L.running[i]];
+      tsvd_status st = TSVD_ERR_HIP;
+      if (q == hipSuccess) {
+        r->info.iters = r->iters.data();
+        r->info.lambda = r->lambda.data();
+        st = batch_problem_result(L.plan, L.run_probs[i], (int)i, &r->info);
+        float tg = 0, te = 0, tf = 0, tt = 0;
+        (void)hipEventElapsedTime(&tg, L.ev[0], L.ev[1]);
+        (void)hipEventElapsedTime(&te, L.ev[1], L.ev[2]);
+        (void)hipEventElapsedTime(&tf, L.ev[2], L.ev[3]);
+        (void)hipEventElapsedTime(&tt, L.ev[0], L.ev[3]);
+        r->info.t_gram_ms = tg;
+        r->info.t_eig_ms = te;
+        r->info.t_final_ms = tf;
+        r->info.t_total_ms = tt;
+        r->info.workspace_bytes = (int64_t)r->footprint;
+        r->info.h2d_bytes = r->loc == TSVD_LOC_PINNED_HOST ? (int64_t)(r->prob.m * r->prob.lda * 4) : 0;
+      } else {
+        s->error = std::string("batch completion: ") + hipGetErrorString(q);
+        (void)hipGetLastError();
+      }
+      release_request(s, r);
+      finish_request(s, r, st);
     }
-    release_request(s, r);
-    finish_request(s, r, st);
+    s->tables.release(L.batch_ws);
+    L.batch_ws = nullptr;
+    L.running.clear();
+    L.active = false;
+    s->cv_done.notify_all();
   }
-  s->tables.release(s->batch_ws);
-  s->batch_ws = nullptr;
-  s->running.clear();
-  s->batch_active = false;
-  s->cv_done.notify_all();
 }
 
 void worker_main(tsvd_server* s) {
@@ -346,8 +374,9 @@ void worker_main(tsvd_server* s) {
     collect(s);
     admit(s);
     launch(s);
-    if (s->stop && s->waiting.empty() && s->admitted.empty() && !s->batch_active) break;
-    if (s->batch_active) {
+    const bool busy = s->busy_lanes() > 0;
+    if (s->stop && s->waiting.empty() && s->admitted.empty() && !busy) break;
+    if (busy) {
       // poll the device batch; new submissions wake the worker early
       s->cv_work.wait_for(lk, std::chrono::microseconds(50));
     } else if (s->waiting.empty() || s->in_flight >= s->cfg.max_slots) {
@@ -370,15 +399,21 @@ tsvd_status tsvd_server_create(tsvd_ctx* ctx, const tsvd_server_config* cfg, tsv
   if (cfg->hbm_budget <= 0) return fail(ctx, TSVD_ERR_INVALID_ARG, "server hbm_budget must be > 0");
   if (cfg->max_slots < 0 || cfg->max_batch < 0) return fail(ctx, TSVD_ERR_INVALID_ARG, "negative slots or batch");
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, TSVD_ERR_HIP, "hipSetDevice");
+  if (cfg->lanes < 0 || cfg->lanes > 8) return fail(ctx, TSVD_ERR_INVALID_ARG, "lanes must be in [0, 8]");
   tsvd_server* s = new tsvd_server();
   s->ctx = ctx;
   s->cfg = *cfg;
   if (s->cfg.max_slots == 0) s->cfg.max_slots = 256;
   if (s->cfg.max_batch == 0 || s->cfg.max_batch > s->cfg.max_slots) s->cfg.max_batch = s->cfg.max_slots;
-  bool ok = hipStreamCreateWithFlags(&s->compute, hipStreamNonBlocking) == hipSuccess &&
-            hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking) == hipSuccess &&
-            hipEventCreateWithFlags(&s->batch_done, hipEventDisableTiming) == hipSuccess;
-  for (int i = 0; i < 4 && ok; i++) ok = hipEventCreate(&s->ev[i]) == hipSuccess;
+  if (s->cfg.lanes == 0) s->cfg.lanes = 2;
+  s->team_cap = std::max(1, ctx->num_cu / s->cfg.lanes);
+  s->lanes.resize(s->cfg.lanes);
+  bool ok = hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking) == hipSuccess;
+  for (Lane& L : s->lanes) {
+    ok = ok && hipStreamCreateWithFlags(&L.compute, hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&L.done, hipEventDisableTiming) == hipSuccess;
+    for (int i = 0; i < 4 && ok; i++) ok = hipEventCreate(&L.ev[i]) == hipSuccess;
+  }
   if (!ok) {
     tsvd_server_destroy(s);
     return fail(ctx, TSVD_ERR_HIP, "server streams/events");
@@ -426,7 +461,7 @@ tsvd_status tsvd_server_submit(tsvd_server* s, const tsvd_problem* p, int32_t lo
     tsvd_problem q = r->prob;
     if (loc == TSVD_LOC_PINNED_HOST) q.A = (const void*)16;  // any aligned non-null stand-in for the check
     std::lock_guard<std::mutex> g(s->mu);
-    const tsvd_status st = batch_plan(s->ctx, 1, &q, one);
+    const tsvd_status st = batch_plan(s->ctx, 1, &q, one, s->team_cap);
     if (st != TSVD_OK) {
       s->error = s->ctx->last_error;
       delete r;
@@ -501,6 +536,8 @@ tsvd_status tsvd_server_get_stats(tsvd_server* s, tsvd_server_stats* out) {
   out->peak_bytes = s->peak_bytes;
   out->in_flight = s->in_flight;
   out->waiting = (int64_t)s->waiting.size();
+  out->lanes_busy_max = s->lanes_busy_max;
+  out->overlapped = s->overlapped;
   std::vector<double> v = s->latencies_ms;
   if (!v.empty()) {
     std::sort(v.begin(), v.end());
@@ -530,18 +567,21 @@ void tsvd_server_destroy(tsvd_server* s) {
   s->cv_work.notify_all();
   if (s->worker.joinable()) s->worker.join();
   (void)hipSetDevice(s->ctx->device);
-  if (s->compute) (void)hipStreamSynchronize(s->compute);
+  for (Lane& L : s->lanes)
+    if (L.compute) (void)hipStreamSynchronize(L.compute);
   if (s->copy) (void)hipStreamSynchronize(s->copy);
   for (auto& kv : s->reqs) {
     if (kv.second->copied) (void)hipEventDestroy(kv.second->copied);
     delete kv.second;
   }
   if (s->pool) (void)hipFree(s->pool);
-  if (s->hpin) (void)hipHostFree(s->hpin);
-  if (s->batch_done) (void)hipEventDestroy(s->batch_done);
-  for (int i = 0; i < 4; i++)
-    if (s->ev[i]) (void)hipEventDestroy(s->ev[i]);
-  if (s->compute) (void)hipStreamDestroy(s->compute);
+  for (Lane& L : s->lanes) {
+    if (L.hpin) (void)hipHostFree(L.hpin);
+    if (L.done) (void)hipEventDestroy(L.done);
+    for (int i = 0; i < 4; i++)
+      if (L.ev[i]) (void)hipEventDestroy(L.ev[i]);
+    if (L.compute) (void)hipStreamDestroy(L.compute);
+  }
   if (s->copy) (void)hipStreamDestroy(s->copy);
   delete s;
 }

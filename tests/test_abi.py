@@ -89,10 +89,12 @@ int main(void) {
   F(tsvd_problem, U) F(tsvd_problem, ldu) F(tsvd_problem, S) F(tsvd_problem, V) F(tsvd_problem, ldv)
   Z(tsvd_problem)
   F(tsvd_server_config, hbm_budget) F(tsvd_server_config, max_slots) F(tsvd_server_config, max_batch)
+  F(tsvd_server_config, lanes)
   Z(tsvd_server_config)
   F(tsvd_server_stats, submitted) F(tsvd_server_stats, batches) F(tsvd_server_stats, mean_batch)
   F(tsvd_server_stats, p50_ms) F(tsvd_server_stats, max_ms) F(tsvd_server_stats, peak_bytes)
-  F(tsvd_server_stats, waiting) Z(tsvd_server_stats)
+  F(tsvd_server_stats, waiting) F(tsvd_server_stats, lanes_busy_max) F(tsvd_server_stats, overlapped)
+  Z(tsvd_server_stats)
   return 0;
 }
 """

@@ -53,8 +53,11 @@ def test_alone_and_in_mix_identical(fresh_ctx):
     assert ia["iters"] == im["iters"]
     assert np.max(np.abs(Sa - dk.s[:6]) / dk.s[:6]) < 1e-6
     assert st["completed"] == 6 and st["failed"] == 0
-    # the same bits again through the one-call batched entry point
+    # the same bits again through the one-call batched entry point, with its
+    # teams capped as the server's two lanes cap them
+    P.set_tuning(fresh_ctx, power_blocks=fresh_ctx.num_cu // 2)
     Ub, Sb, Vb, _ = arrays(P.tsvd_dense_batched(fresh_ctx, [probe], raise_errors=True)[0])
+    P.set_tuning(fresh_ctx)
     assert np.array_equal(Sa, Sb) and np.array_equal(Ua, Ub)
 
 
@@ -134,3 +137,63 @@ def test_submit_rejects_bad_arguments(fresh_ctx):
         # the server keeps working after rejected submissions
         U, S, V, info = arrays(srv.wait(srv.submit(p)))
         assert info["status"] == "TSVD_OK"
+
+
+def hh_request(m, n, k, seed, q, iters):
+    """A = H_L [diag(q^i); 0] H_R built on the device, k start vectors, fixed
+    iteration counts (so the request's duration is known in advance)."""
+    import torch
+    s = synth.spectrum_geometric(q, min(m, n))
+    A = synth.householder_known_torch(m, n, s, seed, torch.device("cuda:0"))
+    st = synth.start_vectors(k, n if m >= n else m, seed=seed + 1)
+    return s, dict(A=A, k=k, eps=0.0, v0=to_dev(st), gram="bf16x3", fixed_iters=[iters] * k)
+
+
+def test_arrival_overlaps_running_batch(fresh_ctx):
+    """Continuous batching across lanes: a small request submitted while a long
+    batch runs is launched on the free lane at once, completes while the long
+    batch is still on the device, and gives the same bits as when it runs
+    alone."""
+    s_long, long_p = hh_request(30000, 4096, 64, seed=501, q=0.99, iters=300)
+    s_small, small_p = hh_request(2000, 300, 4, seed=502, q=0.8, iters=60)
+    with P.Server(fresh_ctx, hbm_budget=4 << 30, lanes=2) as srv:
+        t_long = time.perf_counter()
+        tl = srv.submit(long_p)
+        time.sleep(0.02)  # the long request is on the device now
+        t_small = time.perf_counter()
+        ts = srv.submit(small_p)
+        small = arrays(srv.wait(ts))
+        t_small_seen = time.perf_counter()
+        long_ = arrays(srv.wait(tl))
+        st = srv.stats()
+        alone = arrays(srv.wait(srv.submit(small_p)))
+    done_small = t_small + small[3]["latency_ms"] * 1e-3
+    done_long = t_long + long_[3]["latency_ms"] * 1e-3
+    assert small[3]["status"] == "TSVD_OK" and long_[3]["status"] == "TSVD_OK"
+    assert done_small < done_long, (small[3]["latency_ms"], long_[3]["latency_ms"])
+    assert t_small_seen < done_long
+    assert st["overlapped"] >= 1 and st["lanes_busy_max"] == 2
+    # the same bits alone
+    assert np.array_equal(small[1], alone[1]) and np.array_equal(small[0], alone[0])
+    assert np.array_equal(small[2], alone[2])
+    assert np.max(np.abs(small[1] - s_small[:4]) / s_small[:4]) < 1e-6
+    # the long request is only a timer (300 fixed iterations at a ratio of
+    # 0.98 leave neighbouring triplets partly mixed); its leading sigma has converged
+    assert abs(long_[1][0] - s_long[0]) < 1e-6
+
+
+def test_one_lane_runs_one_batch_at_a_time(fresh_ctx):
+    """lanes = 1: batches never overlap (the server waits for the running batch
+    before it launches the next), and results still meet the closed form."""
+    reqs = [request(3000, 256, 4, seed=600 + i, q=0.8, eps=1e-12) for i in range(6)]
+    with P.Server(fresh_ctx, hbm_budget=1 << 30, lanes=1) as srv:
+        tickets = []
+        for dk, p in reqs:
+            tickets.append(srv.submit(p))
+            time.sleep(0.001)
+        res = [arrays(srv.wait(t)) for t in tickets]
+        st = srv.stats()
+    assert st["overlapped"] == 0 and st["lanes_busy_max"] == 1
+    for (dk, p), (U, S, V, info) in zip(reqs, res):
+        assert info["status"] == "TSVD_OK"
+        assert np.max(np.abs(S - dk.s[:4]) / dk.s[:4]) < 1e-6
