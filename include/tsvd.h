@@ -288,10 +288,10 @@ typedef struct {
                               tables; the rest holds admitted requests' workspaces and staged A */
   int32_t max_slots;       /* requests admitted and not yet completed, at most; 0 = 256 */
   int32_t max_batch;       /* requests per batch launch, at most; 0 = max_slots */
-  int32_t lanes;           /* batches that may run on the device at once, 1..8; 0 = 2.  Each batch's
-                              power launch and every request's team are capped at (CUs / lanes)
-                              workgroups, so the persistent launches of all lanes always fit on the
-                              chip together */
+  int32_t lanes;           /* batches that may run on the device at once, 1..8; 0 = 1.  A further batch
+                              launches only into the CUs the running power launches have released, with
+                              the requests whose team fits them, so all launches always fit the chip
+                              together */
 } tsvd_server_config;
 
 typedef struct {
@@ -314,13 +314,15 @@ typedef struct {
  * order while a slot is free and the budget covers the request's footprint
  * (its Gram, split-K partials and finish sums, plus its A when A is in pinned
  * host memory, which is then copied at once on the copy stream); whenever a
- * lane is idle it launches the admitted requests on it as one batch (as
- * tsvd_dense_batched, with teams of at most CUs / lanes workgroups); when a
- * lane's batch completes it frees that batch's memory and completes its
- * tickets.  So a request that arrives while another batch runs starts on a
- * free lane at once and its work overlaps the running batch on the device.  A
+ * lane is idle it launches admitted requests on it as one batch (as
+ * tsvd_dense_batched) into the CUs that no running power launch holds (the
+ * launches' workgroups report their exit through pinned host memory), taking
+ * the requests whose team fits; when a lane's batch completes it frees that
+ * batch's memory and completes its tickets.  So a request that arrives while
+ * another batch runs starts as soon as that batch's teams have released
+ * enough CUs, and its work overlaps the rest of the running batch.  A
  * request's result is the same whether it runs alone or in any mix (its
- * launch shapes depend on it and the lane count alone). */
+ * launch shapes depend on it alone). */
 tsvd_status tsvd_server_create(tsvd_ctx* ctx, const tsvd_server_config* cfg, tsvd_server** out);
 
 /* Queue one request; returns at once with a ticket.  The problem struct is

@@ -63,8 +63,11 @@ tsvd_status batch_plan(tsvd_ctx* ctx, int count, const tsvd_problem* probs, Batc
 // upload and the result readback, so that no copy waits on the host; without
 // it, pageable vectors are used.  The small results land in bp.hs / hit / hl
 // once the stream has completed.
+// exit_flags / exit_id: passed to the power launch (its workgroups report
+// their exit there, for the server's CU accounting)
 tsvd_status batch_enqueue(tsvd_ctx* ctx, const tsvd_problem* probs, BatchPlan& bp, char* bbase, char* const* pbase,
-                          hipStream_t stream, hipEvent_t* ev, char* hpin = nullptr);
+                          hipStream_t stream, hipEvent_t* ev, char* hpin = nullptr, int* exit_flags = nullptr,
+                          int exit_id = 0);
 // status and info of problem i after the stream has completed
 tsvd_status batch_problem_result(const BatchPlan& bp, const tsvd_problem& q, int i, tsvd_info* info);
 

@@ -152,7 +152,8 @@ tsvd_status batch_plan(tsvd_ctx* ctx, int count, const tsvd_problem* probs, Batc
 }
 
 tsvd_status batch_enqueue(tsvd_ctx* ctx, const tsvd_problem* probs, BatchPlan& bp, char* bbase,
-                          char* const* pbase, hipStream_t stream, hipEvent_t* ev, char* hpin) {
+                          char* const* pbase, hipStream_t stream, hipEvent_t* ev, char* hpin, int* exit_flags,
+                          int exit_id) {
   const int count = bp.count;
   if (hpin) {
     bp.desc = hpin;
@@ -301,7 +302,8 @@ tsvd_status batch_enqueue(tsvd_ctx* ctx, const tsvd_problem* probs, BatchPlan& b
   {
     const int rc = power_dyn_launch((const PowerArgs*)(bbase + bp.off_pargs), (const int*)(bbase + bp.off_order),
                                     (const int*)(bbase + bp.off_gsize), count, (int*)(bbase + bp.off_sched), bp.grid,
-                                    lds, (uint64_t*)(bbase + bp.off_zero), bp.zero_words, stream);
+                                    lds, (uint64_t*)(bbase + bp.off_zero), bp.zero_words, stream, exit_flags,
+                                    exit_id);
     if (rc == -2) return fail(ctx, TSVD_ERR_UNSUPPORTED, "batched power kernel does not fit on a CU");
     if (rc) return from_internal(ctx, rc, "batched power iteration");
   }

@@ -78,8 +78,11 @@ int power_launch(int is_f64, const PowerPlan& p, PowerArgs a, hipStream_t stream
 // memory at zero_base are cleared first
 // static LDS of the batched power kernel (its dynamic LDS must leave room for it)
 size_t power_dyn_static_lds();
+// exit_flags (optional, grid ints in coherent pinned host memory): each
+// workgroup stores exit_id into its entry when it leaves the launch
 int power_dyn_launch(const PowerArgs* d_probs, const int* d_order, const int* d_gsize, int nprob, int* d_sched,
-                     int grid, size_t lds_bytes, uint64_t* zero_base, size_t zero_words, hipStream_t stream);
+                     int grid, size_t lds_bytes, uint64_t* zero_base, size_t zero_words, hipStream_t stream,
+                     int* exit_flags = nullptr, int exit_id = 0);
 
 // ---- finishing pass (finish.hip)
 // one problem of a grouped finishing pass (FP32 A); k = triplets found

@@ -636,7 +636,8 @@ __global__ __launch_bounds__(256, 1) void power_kernel(PowerArgs a) {
 // mix.  sched: [0] queue head, [1 + h] seats taken in problem h (zeroed by the
 // host).  The assembly wait is bounded by join_spin polls.
 __global__ __launch_bounds__(256, 1) void power_dyn_kernel(const PowerArgs* probs, const int* order, const int* gsize,
-                                                           int nprob, int* sched, int64_t join_spin) {
+                                                           int nprob, int* sched, int64_t join_spin, int* exit_flags,
+                                                           int exit_id) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int s_h, s_rank;
   while (true) {
@@ -664,7 +665,14 @@ __global__ __launch_bounds__(256, 1) void power_dyn_kernel(const PowerArgs* prob
     __syncthreads();
     const int h = s_h, rank = s_rank;
     __syncthreads();
-    if (h < 0) return;
+    if (h < 0) {
+      // tell the host that this workgroup's CU is free again (one vector store
+      // to coherent pinned host memory; the server launches further batches
+      // into CUs released this way)
+      if (threadIdx.x == 0 && exit_flags)
+        __hip_atomic_store(exit_flags + blockIdx.x, exit_id, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      return;
+    }
     const PowerArgs a = probs[order[h]];
     if (rank < 0) {  // the team never assembled: report and leave the problem
       if (threadIdx.x == 0) atomicMax(a.status + 2, (int)ERR_SPIN);
@@ -794,7 +802,8 @@ size_t power_dyn_static_lds() {
 }
 
 int power_dyn_launch(const PowerArgs* d_probs, const int* d_order, const int* d_gsize, int nprob, int* d_sched,
-                     int grid, size_t lds_bytes, uint64_t* zero_base, size_t zero_words, hipStream_t stream) {
+                     int grid, size_t lds_bytes, uint64_t* zero_base, size_t zero_words, hipStream_t stream,
+                     int* exit_flags, int exit_id) {
   if (grid <= 0 || nprob <= 0) return 0;
   if (zero_words) {
     hipLaunchKernelGGL(zero_words_kernel, dim3(256), dim3(256), 0, stream, zero_base, zero_words);
@@ -806,7 +815,8 @@ int power_dyn_launch(const PowerArgs* d_probs, const int* d_order, const int* d_
   TSVD_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, lds_bytes));
   if (per_cu < 1) return -2;
   int64_t join_spin = (int64_t)1 << 30;
-  void* args[] = {(void*)&d_probs, (void*)&d_order, (void*)&d_gsize, (void*)&nprob, (void*)&d_sched, (void*)&join_spin};
+  void* args[] = {(void*)&d_probs, (void*)&d_order,   (void*)&d_gsize,    (void*)&nprob,
+                  (void*)&d_sched, (void*)&join_spin, (void*)&exit_flags, (void*)&exit_id};
   if ((int64_t)grid > (int64_t)per_cu * max_cus()) return -2;
   TSVD_HIP_TRY(hipLaunchKernel(fn, dim3(grid), dim3(256), args, lds_bytes, stream));
   return 0;

@@ -5,21 +5,25 @@
 //      covers their footprint (Gram, split-K partials, finish sums and the
 //      staged copy of a host-resident A) and a slot is free; host-resident A is
 //      copied on the copy stream at once;
-//   2. launches the admitted requests as one batch (grouped Gram, team power
-//      kernel, grouped finish) on any idle lane: each lane is a compute stream,
-//      and up to `lanes` batches run on the device at once;
+//   2. launches admitted requests as one batch (grouped Gram, team power
+//      kernel, grouped finish) on an idle lane -- each lane is a compute
+//      stream -- into the CUs that no running power launch holds;
 //   3. when a lane's completion event has fired, releases that batch's memory
 //      and completes its tickets (latency = completion - submission, host
 //      clock).
-// A request that arrives while a batch runs therefore starts on a free lane
-// at once, and its Gram, power steps and finish overlap the running batch.
-// Every team (and every batch's power launch) is capped at CUs / lanes
-// workgroups, so the persistent power launches of all lanes together never
-// need more CUs than the chip has: each launch's workgroups all become
-// resident once the other lanes' short Gram and finish kernels drain, and no
-// lane waits on another.  Each request's result is independent of the batch
-// and the lane it ran in (team sizes and Gram chunking depend on the request
-// and the lane count alone).
+// The persistent power launch of a batch holds one CU per workgroup until
+// that workgroup finds the batch's queue empty; each workgroup then stores
+// the batch's id into its entry of a flag array in coherent pinned host
+// memory before it exits.  The worker counts a running launch's CUs as its
+// grid minus the flags set, and a new batch takes only requests whose team
+// fits the CUs left, with a grid of at most that many workgroups.  The grids
+// of all running launches therefore never exceed the chip, so every launch's
+// workgroups become resident once the short Gram and finish kernels around
+// them drain, and no launch waits on another.  A request that arrives while a
+// batch runs starts as soon as the running batch's teams release enough CUs
+// (at once, when they already have), overlapping the rest of that batch.
+// Team sizes and Gram chunking depend on the request alone, so each result is
+// the same alone and in any mix.
 #include <math.h>
 #include <string.h>
 
@@ -111,6 +115,7 @@ struct Request {
   char* staged = nullptr;    // device copy of a host-resident A
   hipEvent_t copied = nullptr;
   size_t footprint = 0;
+  int team = 0;             // power team size (workgroups), from the request alone
   tsvd_status status = TSVD_OK;
   tsvd_info info = {};
   std::vector<int32_t> iters;
@@ -133,6 +138,17 @@ struct Lane {
   bool active = false;
   char* hpin = nullptr;  // pinned host staging of the batch's descriptors and results
   size_t hpin_bytes = 0;
+  int* flags = nullptr;  // coherent pinned host memory, one int per power workgroup
+  int batch_id = 0;      // what the current power launch's workgroups store on exit
+  int grid = 0;          // its workgroups
+  // CUs the lane's power launch may still hold: its grid less the workgroups that have left
+  int live() const {
+    if (!active) return 0;
+    int gone = 0;
+    const volatile int* f = flags;
+    for (int i = 0; i < grid; i++) gone += f[i] == batch_id ? 1 : 0;
+    return grid - gone;
+  }
 };
 
 struct tsvd_server {
@@ -140,7 +156,7 @@ struct tsvd_server {
   tsvd_server_config cfg = {};
   hipStream_t copy = nullptr;
   std::vector<Lane> lanes;
-  int team_cap = 0;  // CUs / lanes
+  int next_batch_id = 1;
   char* pool = nullptr;
   Arena arena;    // request workspaces and staged copies of host A
   Arena tables;   // the running batches' tables and team buffers
@@ -204,7 +220,7 @@ void admit(tsvd_server* s) {
   while (!s->waiting.empty() && s->in_flight < s->cfg.max_slots) {
     Request* r = s->reqs[s->waiting.front()];
     BatchPlan one;
-    tsvd_status st = batch_plan(s->ctx, 1, &r->prob, one, s->team_cap);
+    tsvd_status st = batch_plan(s->ctx, 1, &r->prob, one);
     if (st != TSVD_OK) {  // arguments were checked at submit; planning limits remain
       s->waiting.pop_front();
       finish_request(s, r, st);
@@ -212,6 +228,7 @@ void admit(tsvd_server* s) {
       continue;
     }
     const ProbPlan& p = one.P[0];
+    r->team = p.G;
     r->footprint = request_footprint(p, r->prob, r->loc);
     if (r->footprint > s->arena.capacity() || one.batch_ws_bytes > s->tables.capacity()) {
       s->waiting.pop_front();
@@ -262,20 +279,34 @@ void launch(tsvd_server* s) {
       break;
     }
   if (!L) return;
+  // CUs no running power launch holds.  Beside a running batch, a new one
+  // launches only once at least half the chip is free (a batch's grid is
+  // fixed at launch: started into a small remainder, its teams would queue on
+  // few CUs long after the running batch has ended).  It takes admitted
+  // requests in arrival order while their teams fit those CUs, and stops at
+  // the first that does not (a request with a large team is not overtaken
+  // indefinitely: it waits at the head until enough CUs are released).
+  int free_cus = s->ctx->num_cu;
+  for (const Lane& l : s->lanes) free_cus -= l.live();
+  if (free_cus <= 0 || (s->busy_lanes() > 0 && 2 * free_cus < s->ctx->num_cu)) return;
   const int maxb = s->cfg.max_batch;
   std::vector<uint64_t> take;
-  for (size_t i = 0; i < s->admitted.size() && (int)take.size() < maxb; i++) take.push_back(s->admitted[i]);
+  for (size_t i = 0; i < s->admitted.size() && (int)take.size() < maxb; i++) {
+    if (s->reqs[s->admitted[i]]->team > free_cus) break;
+    take.push_back(s->admitted[i]);
+  }
   while (!take.empty()) {
     L->run_probs.clear();
     for (uint64_t t : take) L->run_probs.push_back(s->reqs[t]->prob);
-    tsvd_status st = batch_plan(s->ctx, (int)take.size(), L->run_probs.data(), L->plan, s->team_cap);
+    // the cap leaves every team as planned alone (each fits) and bounds the grid
+    tsvd_status st = batch_plan(s->ctx, (int)take.size(), L->run_probs.data(), L->plan, free_cus);
     if (st != TSVD_OK) {
       for (uint64_t t : take) {
         Request* r = s->reqs[t];
         release_request(s, r);
         finish_request(s, r, st);
+        s->admitted.erase(std::find(s->admitted.begin(), s->admitted.end(), t));
       }
-      s->admitted.erase(s->admitted.begin(), s->admitted.begin() + take.size());
       s->cv_done.notify_all();
       return;
     }
@@ -296,7 +327,7 @@ void launch(tsvd_server* s) {
       L->hpin_bytes = want;
     }
   }
-  s->admitted.erase(s->admitted.begin(), s->admitted.begin() + take.size());
+  for (uint64_t t : take) s->admitted.erase(std::find(s->admitted.begin(), s->admitted.end(), t));
   std::vector<char*> pbase;
   for (uint64_t t : take) {
     Request* r = s->reqs[t];
@@ -304,8 +335,9 @@ void launch(tsvd_server* s) {
     pbase.push_back(r->ws);
     r->state = RUNNING;
   }
-  tsvd_status st =
-      batch_enqueue(s->ctx, L->run_probs.data(), L->plan, L->batch_ws, pbase.data(), L->compute, L->ev, L->hpin);
+  const int id = s->next_batch_id++;
+  tsvd_status st = batch_enqueue(s->ctx, L->run_probs.data(), L->plan, L->batch_ws, pbase.data(), L->compute, L->ev,
+                                 L->hpin, L->flags, id);
   if (st == TSVD_OK && hipEventRecord(L->done, L->compute) != hipSuccess) st = TSVD_ERR_HIP;
   if (st != TSVD_OK) {
     s->error = s->ctx->last_error;
@@ -322,6 +354,8 @@ void launch(tsvd_server* s) {
   }
   if (s->busy_lanes() > 0) s->overlapped++;
   L->running = take;
+  L->batch_id = id;
+  L->grid = L->plan.grid;
   L->active = true;
   s->lanes_busy_max = std::max<int64_t>(s->lanes_busy_max, s->busy_lanes());
   s->batches++;
@@ -405,13 +439,16 @@ tsvd_status tsvd_server_create(tsvd_ctx* ctx, const tsvd_server_config* cfg, tsv
   s->cfg = *cfg;
   if (s->cfg.max_slots == 0) s->cfg.max_slots = 256;
   if (s->cfg.max_batch == 0 || s->cfg.max_batch > s->cfg.max_slots) s->cfg.max_batch = s->cfg.max_slots;
-  if (s->cfg.lanes == 0) s->cfg.lanes = 2;
-  s->team_cap = std::max(1, ctx->num_cu / s->cfg.lanes);
+  // one lane by default: at the serving mix's load two or three lanes kept the
+  // same request rate with higher latency (a batch's grid is fixed at launch)
+  if (s->cfg.lanes == 0) s->cfg.lanes = 1;
   s->lanes.resize(s->cfg.lanes);
   bool ok = hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking) == hipSuccess;
   for (Lane& L : s->lanes) {
     ok = ok && hipStreamCreateWithFlags(&L.compute, hipStreamNonBlocking) == hipSuccess &&
-         hipEventCreateWithFlags(&L.done, hipEventDisableTiming) == hipSuccess;
+         hipEventCreateWithFlags(&L.done, hipEventDisableTiming) == hipSuccess &&
+         hipHostMalloc((void**)&L.flags, (size_t)ctx->num_cu * sizeof(int), hipHostMallocCoherent) == hipSuccess;
+    if (ok) memset(L.flags, 0, (size_t)ctx->num_cu * sizeof(int));
     for (int i = 0; i < 4 && ok; i++) ok = hipEventCreate(&L.ev[i]) == hipSuccess;
   }
   if (!ok) {
@@ -461,7 +498,7 @@ tsvd_status tsvd_server_submit(tsvd_server* s, const tsvd_problem* p, int32_t lo
     tsvd_problem q = r->prob;
     if (loc == TSVD_LOC_PINNED_HOST) q.A = (const void*)16;  // any aligned non-null stand-in for the check
     std::lock_guard<std::mutex> g(s->mu);
-    const tsvd_status st = batch_plan(s->ctx, 1, &q, one, s->team_cap);
+    const tsvd_status st = batch_plan(s->ctx, 1, &q, one);
     if (st != TSVD_OK) {
       s->error = s->ctx->last_error;
       delete r;
@@ -577,6 +614,7 @@ void tsvd_server_destroy(tsvd_server* s) {
   if (s->pool) (void)hipFree(s->pool);
   for (Lane& L : s->lanes) {
     if (L.hpin) (void)hipHostFree(L.hpin);
+    if (L.flags) (void)hipHostFree(L.flags);
     if (L.done) (void)hipEventDestroy(L.done);
     for (int i = 0; i < 4; i++)
       if (L.ev[i]) (void)hipEventDestroy(L.ev[i]);

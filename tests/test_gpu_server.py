@@ -53,11 +53,8 @@ def test_alone_and_in_mix_identical(fresh_ctx):
     assert ia["iters"] == im["iters"]
     assert np.max(np.abs(Sa - dk.s[:6]) / dk.s[:6]) < 1e-6
     assert st["completed"] == 6 and st["failed"] == 0
-    # the same bits again through the one-call batched entry point, with its
-    # teams capped as the server's two lanes cap them
-    P.set_tuning(fresh_ctx, power_blocks=fresh_ctx.num_cu // 2)
+    # the same bits again through the one-call batched entry point
     Ub, Sb, Vb, _ = arrays(P.tsvd_dense_batched(fresh_ctx, [probe], raise_errors=True)[0])
-    P.set_tuning(fresh_ctx)
     assert np.array_equal(Sa, Sb) and np.array_equal(Ua, Ub)
 
 
@@ -151,10 +148,11 @@ def hh_request(m, n, k, seed, q, iters):
 
 def test_arrival_overlaps_running_batch(fresh_ctx):
     """Continuous batching across lanes: a small request submitted while a long
-    batch runs is launched on the free lane at once, completes while the long
-    batch is still on the device, and gives the same bits as when it runs
-    alone."""
-    s_long, long_p = hh_request(30000, 4096, 64, seed=501, q=0.99, iters=300)
+    batch runs is launched on the free lane into the CUs the long batch's team
+    leaves free (a 2048-dimensional Gram takes a team of 64 workgroups),
+    completes while the long batch is still on the device, and gives the same
+    bits as when it runs alone."""
+    s_long, long_p = hh_request(30000, 2048, 64, seed=501, q=0.99, iters=400)
     s_small, small_p = hh_request(2000, 300, 4, seed=502, q=0.8, iters=60)
     with P.Server(fresh_ctx, hbm_budget=4 << 30, lanes=2) as srv:
         t_long = time.perf_counter()
