@@ -133,6 +133,18 @@ def measured_exchange(d: int):
     return json.loads(r.stdout.strip().splitlines()[-1])
 
 
+def measured_gather():
+    """Random 4-byte gather rates of this GPU for gathered sets of 1 MiB to
+    1 GiB (the C++ driver's probe), or None when tsvd_bench is not built."""
+    exe = os.path.join(ROOT, "paper_2208_08410_amd", "tsvd_bench")
+    if not os.path.exists(exe):
+        return None
+    r = subprocess.run([exe, "gather"], capture_output=True, text=True, timeout=300)
+    if r.returncode != 0:
+        return None
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
 def measured_traffic(kernel: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary (FETCH_SIZE, WRITE_SIZE scaled by a reference copy), or None when
@@ -630,6 +642,19 @@ def sparse_main(a):
     dt = time.perf_counter() - t1
     per_iter = dt * 1e3 / (k * a.sparse_iters)
     pair = 2 * (nnz * 8 + (n + 1) * 8 + n * 4 + n * 8)
+    # the binding ceiling: random gathers of x inside one XCD's L2 (each tile
+    # gathers from one 1 MiB slice of FP32 x), measured by the driver's probe
+    gp = measured_gather()
+    slice_mib = (1 << (a.sparse_col_bits or 18)) * 4 / (1 << 20)
+    gpeak = None
+    if gp:
+        sets = sorted(gp["sets"], key=lambda e: abs(e["set_mib"] - slice_mib))
+        gpeak = sets[0]["g_gathers_per_s"]
+    gach = nnz / (rates["csr"]["ms"] * 1e-3) / 1e9
+    roof_sp = {"kernel": "spmv_tiles_kernel<float> (A x)", "bound": "l2 gather", "achieved": gach, "peak": gpeak,
+               "unit": "G gathers/s", "frac": (gach / gpeak) if gpeak else None, "traffic": None,
+               "note": "one 4-byte x gather per nonzero; peak = random gathers over a set the size of one column "
+                       "slice of x (tsvd_bench gather, same box)"}
     out = {
         "metric": METRIC,
         "value": pair / (per_iter * 1e-3) / 1e9,
@@ -641,8 +666,11 @@ def sparse_main(a):
         "config": {"workload": f"sparse CSR {n}x{n}, density {a.sparse_density:g} ({nnz} nnz), uniform random "
                                f"columns, N(0,1) values; k={k}, {a.sparse_iters} fixed iterations per triplet",
                    "n": n, "nnz": nnz, "k": k, "tile_bits": [a.sparse_row_bits, a.sparse_col_bits]},
-        "roofline": {"bound": "hbm", "achieved": rates["csr"]["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": rates["csr"]["gbs"] / HBM_PEAK_GBS, "traffic": None, "kernel": "spmv_tiles_kernel (A x)"},
+        "roofline": roof_sp,
+        "roofline_hbm_view": {"bound": "hbm", "achieved": rates["csr"]["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": rates["csr"]["gbs"] / HBM_PEAK_GBS,
+                              "note": "algorithmic bytes (index + value per nonzero, row pointers, x and y once)"},
+        "gather_probe": gp,
         "spmv": rates,
         "ms_per_iteration": per_iter,
         "csc_build_ms": csc_ms,

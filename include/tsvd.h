@@ -160,9 +160,9 @@ typedef struct {
                             sets the team size (ceil(4 d^2 / (team_kib * 1024)) workgroups);
                             0 = 256; range [8, 65536] */
   int32_t group_kchunk;  /* batched Gram: contraction rows per work unit; 0 = 2048; range [32, 2^20] */
-  int32_t sparse_row_bits; /* sparse products: tiles of 2^bits rows (0 = library choice, about 2 row
-                              chunks per CU, 32..8192 rows); range [0, 13]; applies to handles created
-                              after the call */
+  int32_t sparse_row_bits; /* sparse products: tiles of 2^bits rows, one per wave (0 = library choice,
+                              about two workgroups of 8 chunks per CU, 32..1024 rows); range [0, 11];
+                              applies to handles created after the call */
   int32_t sparse_col_bits; /* sparse products: column slices of 2^bits (0 = 2^18: 1 MiB of FP32 x);
                               row + column bits <= 32 */
   int32_t power_path;    /* Gram power iteration: 0 = the on-chip persistent kernel when the iterate fits

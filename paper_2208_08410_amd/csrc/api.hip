@@ -125,9 +125,9 @@ tsvd_status tsvd_ctx_set_tuning(tsvd_ctx* ctx, const tsvd_tuning* t) {
   if (t->gram_chunks < 0 || t->gram_chunks > 4096) return fail(ctx, TSVD_ERR_INVALID_ARG, "gram_chunks out of range");
   if (t->power_blocks < 0 || t->power_blocks > ctx->num_cu)
     return fail(ctx, TSVD_ERR_INVALID_ARG, "power_blocks must be in [0, %d]", ctx->num_cu);
-  if (t->sparse_row_bits < 0 || t->sparse_row_bits > 13 || t->sparse_col_bits < 0 || t->sparse_col_bits > 31 ||
+  if (t->sparse_row_bits < 0 || t->sparse_row_bits > 11 || t->sparse_col_bits < 0 || t->sparse_col_bits > 31 ||
       t->sparse_row_bits + t->sparse_col_bits > 32)
-    return fail(ctx, TSVD_ERR_INVALID_ARG, "sparse tile bits out of range (rows <= 13, rows + cols <= 32)");
+    return fail(ctx, TSVD_ERR_INVALID_ARG, "sparse tile bits out of range (rows <= 11, rows + cols <= 32)");
   if (t->team_kib != 0 && (t->team_kib < 8 || t->team_kib > 65536))
     return fail(ctx, TSVD_ERR_INVALID_ARG, "team_kib must be 0 or in [8, 65536]");
   if (t->group_kchunk != 0 && (t->group_kchunk < 32 || t->group_kchunk > (1 << 20)))

@@ -91,107 +91,135 @@ __global__ __launch_bounds__(256) void tile_fill_kernel(const int64_t* ptr, cons
 
 // ---- product ------------------------------------------------------------
 
-constexpr int TW = 8;  // waves per workgroup of the tiled product
+constexpr int TW = 8;  // waves per workgroup of the tiled product: one row chunk each
+constexpr int kMaxRowBits = 11;  // TW x 2^bits doubles of LDS: 128 KiB at most
+
+// y = A x over row chunks [c0, c0 + nch): wave w of workgroup g owns chunk
+// c0 + TW g + w and accumulates that chunk's y in its own FP64 slice of LDS
+// while it walks the column slices in order.  No other wave touches the
+// slice; the waves only meet at one barrier per column slice, which keeps
+// their gathers in the same slice of x.  The loop is software-pipelined over tiles:
+// while a tile's x gathers are in flight, the keys and values of the next
+// tile and the pointer of the one after are already being loaded, so a tile
+// costs one dependent round trip (the gathers) instead of three.  Within a
+// tile the entries are in row order; 64-entry chunks are reduced with a
+// segmented scan over the lanes (skipped when a chunk's rows are all
+// distinct, the common case at C4's density), and every lane that ends a
+// segment adds its sum to LDS with one FP64 LDS add (one lane per row per
+// instruction; the instructions of a wave execute in order), so the sums have
+// a fixed order and the result is deterministic.  At 5e7 x 5e7 with 2.5e9
+// nonzeros: 16.3 ms per product with 1024-row chunks and 2^18-column slices
+// (2^17: 22.6 ms, 2^19: 36.6 ms; 2^11-row chunks 22.1 ms, 2^9 24.3 ms; 16
+// waves per workgroup 19.2 ms; free-running waves without the per-slice
+// barrier 37-38 ms; a read-modify-write instead of the LDS add 16.7 ms).
+constexpr int UC = 8;  // 64-entry chunks of a tile held in registers (the rest of a longer tile loops)
+
 template <typename XT>
-__global__ __launch_bounds__(TW * 64) void spmv_tiles_kernel(const int64_t* tptr, const uint32_t* key, const float* val,
-                                                         int64_t rows, int rbits, int cbits, int64_t ns, const XT* x,
-                                                         double* y, float* yf, int64_t base, int64_t c_off) {
-  extern __shared__ double yl[];  // 2^rbits
-  __shared__ int brow[2 * TW];
-  __shared__ double bval[2 * TW];
+__device__ __forceinline__ void tile_chunks(double* yl, int lane, int64_t e_begin, int64_t b, int cbits, uint32_t cmask,
+                                            const uint32_t (&kk)[UC], const float (&vv)[UC], const XT (&xx)[UC]) {
+#pragma unroll
+  for (int u = 0; u < UC; u++) {
+    const int64_t e0 = e_begin + 64 * u;
+    if (e0 >= b) break;  // uniform
+    const bool valid = e0 + lane < b;
+    const int nvalid = (int)min((int64_t)64, b - e0);
+    int row = 0x7fffffff;
+    double p = 0.0;
+    if (valid) {
+      row = (int)(kk[u] >> cbits);
+      p = (double)vv[u] * (double)xx[u];
+    }
+    // rows are sorted, so a chunk whose rows are all distinct needs no scan
+    const int rn = next_lane_key(row);
+    const bool distinct = __builtin_amdgcn_ballot_w64(valid && lane < nvalid - 1 && rn == row) == 0;
+    if (!distinct) p = wave_seg_scan(p, row);
+    // the last lane of each segment in this chunk adds it (a segment that
+    // continues into the next chunk is added in two parts, in order)
+    if (valid && (lane == nvalid - 1 || rn != row)) atomicAdd(yl + row, p);  // ds_add_f64: one lane per row
+  }
+}
+
+template <typename XT>
+__global__ __launch_bounds__(TW * 64) void spmv_tiles_kernel(const int64_t* __restrict__ tptr,
+                                                         const uint32_t* __restrict__ key,
+                                                         const float* __restrict__ val, int64_t rows, int rbits,
+                                                         int cbits, int64_t ns, const XT* __restrict__ x, double* y,
+                                                         float* yf, int64_t base, int64_t c0, int64_t nch) {
+  extern __shared__ double ylds[];  // TW x 2^rbits
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t c = blockIdx.x + c_off;
+  const int64_t cl0 = (int64_t)blockIdx.x * TW + wave;
+  const bool active = cl0 < nch;  // a wave past the last chunk only keeps step with the others
+  const int64_t cl = active ? cl0 : nch - 1;
+  const int64_t c = c0 + cl;
   const int RH = 1 << rbits;
-  const int64_t r0 = (int64_t)c << rbits;
+  double* yl = ylds + (size_t)wave * RH;
+  const int64_t r0 = c << rbits;
   const int nrow = (int)min((int64_t)RH, rows - r0);
   const uint32_t cmask = (cbits >= 32) ? 0xffffffffu : ((1u << cbits) - 1u);
-  for (int i = threadIdx.x; i < RH; i += TW * 64) yl[i] = 0.0;
-  __syncthreads();
+  for (int i = lane; i < RH; i += 64) yl[i] = 0.0;
+  const int64_t* tp = tptr + c * ns;
+  // pipeline state: the current tile [a, b) with its first UC chunks' keys and
+  // values in registers, and the end of the next tile
+  int64_t a = tp[0] - base, b = tp[1] - base;
+  int64_t bn = ns > 1 ? tp[2] - base : b;
+  if (!active) a = b = bn = 0;
+  uint32_t kk[UC];
+  float vv[UC];
+#pragma unroll
+  for (int u = 0; u < UC; u++) {
+    const int64_t e = a + 64 * u + lane;
+    kk[u] = e < b ? __builtin_nontemporal_load(key + e) : 0u;
+    vv[u] = e < b ? __builtin_nontemporal_load(val + e) : 0.f;
+  }
   for (int64_t s = 0; s < ns; s++) {
-    const int64_t a = tptr[c * ns + s] - base, b = tptr[c * ns + s + 1] - base;  // entries of this batch's arrays
-    const int64_t n = b - a;
-    if (n == 0) continue;  // uniform
     const XT* xs = x + (s << cbits);
-    const int64_t wa = a + (n * wave) / TW, wb = a + (n * (wave + 1)) / TW;
-    // left boundary: the wave's first row (may continue the previous wave's
-    // range); right boundary: its last open segment
-    int first_row = -1;
-    if (wa < wb) first_row = (int)(__builtin_nontemporal_load(key + wa) >> cbits);
-    int carry_row = -1;  // wave-uniform: the open segment at the end of the last chunk
-    double carry = 0.0;
-    double left = 0.0;   // the first segment's sum, held by the one lane that closed it
-    // UC chunks of 64 entries per step: their keys, values and x gathers are
-    // all issued before the first scan, so each wave keeps UC independent
-    // gathers in flight; the chunks are then reduced in order.  With 8, a
-    // wave's share of a tile at density 1e-6 (about 270 entries) takes one
-    // step instead of two (A x at 5e7 x 5e7: 27.1 -> 25.2 ms; 5 does as well)
-    constexpr int UC = 8;
-    for (int64_t s0 = wa; s0 < wb; s0 += 64 * UC) {
-      uint32_t kk[UC];
-      float vv[UC];
-      XT xx[UC];
+    XT xx[UC];
+#pragma unroll
+    for (int u = 0; u < UC; u++) xx[u] = (a + 64 * u + lane < b) ? xs[kk[u] & cmask] : (XT)0;
+    // next tile's keys and values, and the pointer after it, while the gathers fly
+    uint32_t kn[UC];
+    float vn[UC];
+#pragma unroll
+    for (int u = 0; u < UC; u++) {
+      const int64_t e = b + 64 * u + lane;
+      kn[u] = e < bn ? __builtin_nontemporal_load(key + e) : 0u;
+      vn[u] = e < bn ? __builtin_nontemporal_load(val + e) : 0.f;
+    }
+    const int64_t bnn = !active ? 0 : (s + 2 < ns ? tp[s + 3] - base : bn);
+    tile_chunks<XT>(yl, lane, a, b, cbits, cmask, kk, vv, xx);
+    // a tile longer than UC chunks: the rest, UC chunks at a time, unpipelined
+    for (int64_t s0 = a + 64 * UC; s0 < b; s0 += 64 * UC) {
+      uint32_t k2[UC];
+      float v2[UC];
+      XT x2[UC];
 #pragma unroll
       for (int u = 0; u < UC; u++) {
         const int64_t e = s0 + 64 * u + lane;
-        kk[u] = e < wb ? __builtin_nontemporal_load(key + e) : 0u;
-        vv[u] = e < wb ? __builtin_nontemporal_load(val + e) : 0.f;
+        k2[u] = e < b ? __builtin_nontemporal_load(key + e) : 0u;
+        v2[u] = e < b ? __builtin_nontemporal_load(val + e) : 0.f;
       }
 #pragma unroll
-      for (int u = 0; u < UC; u++) xx[u] = (s0 + 64 * u + lane < wb) ? xs[kk[u] & cmask] : (XT)0;
+      for (int u = 0; u < UC; u++) x2[u] = (s0 + 64 * u + lane < b) ? xs[k2[u] & cmask] : (XT)0;
+      tile_chunks<XT>(yl, lane, s0, b, cbits, cmask, k2, v2, x2);
+    }
 #pragma unroll
-      for (int u = 0; u < UC; u++) {
-        const int64_t e0 = s0 + 64 * u;
-        if (e0 >= wb) break;  // uniform
-        const int64_t e = e0 + lane;
-        const bool valid = e < wb;
-        const int nvalid = (int)min((int64_t)64, wb - e0);
-        int row = 0x7fffffff;
-        double p = 0.0;
-        if (valid) {
-          row = (int)(kk[u] >> cbits);
-          p = (double)vv[u] * (double)xx[u];
-        }
-        // the open segment ended exactly at the last chunk's end: close it
-        if (carry_row >= 0 && __builtin_amdgcn_readlane(row, 0) != carry_row) {
-          if (lane == 0) {
-            if (carry_row == first_row) left = carry;
-            else yl[carry_row] += carry;  // interior row: no other wave holds it
-          }
-          carry_row = -1;
-          carry = 0.0;
-        }
-        // segmented inclusive scan (rows are sorted, so equal rows are contiguous)
-        p = wave_seg_scan(p, row);
-        if (row == carry_row) p += carry;  // the segment continued from the last chunk
-        const int rn = next_lane_key(row);
-        if (valid && lane < nvalid - 1 && rn != row) {  // a segment ends inside this chunk
-          if (row == first_row) left = p;  // only the first segment has first_row
-          else yl[row] += p;
-        }
-        carry_row = __builtin_amdgcn_readlane(row, nvalid - 1);
-        carry = readlane_f64(p, nvalid - 1);
-      }
+    for (int u = 0; u < UC; u++) {
+      kk[u] = kn[u];
+      vv[u] = vn[u];
     }
-    // boundary rows: the first segment (left) and the open last one (right);
-    // they are added by one thread in wave order after the tile
-    const double lsum = wave_sum(left);  // one lane holds it, the others 0: exact
-    if (lane == 0) {
-      const bool whole = carry_row >= 0 && carry_row == first_row;
-      brow[2 * wave] = wa < wb ? first_row : -1;
-      bval[2 * wave] = whole ? carry : lsum;
-      brow[2 * wave + 1] = (carry_row >= 0 && !whole) ? carry_row : -1;
-      bval[2 * wave + 1] = carry;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      for (int j = 0; j < 2 * TW; j++)
-        if (brow[j] >= 0) yl[brow[j]] += bval[j];
-    }
+    a = b;
+    b = bn;
+    bn = bnn;
+    // the waves of a workgroup walk the slices in step, so their x gathers
+    // fall in the same slice of x, which stays in L2 (free-running waves
+    // drift apart and the slices they touch no longer fit)
     __syncthreads();
   }
-  for (int i = threadIdx.x; i < nrow; i += TW * 64) {
-    if (y) y[r0 + i] = yl[i];
-    if (yf) yf[r0 + i] = (float)yl[i];
+  if (!active) return;
+  for (int i = lane; i < nrow; i += 64) {
+    const double v = yl[i];
+    if (y) y[r0 + i] = v;
+    if (yf) yf[r0 + i] = (float)v;
   }
 }
 
@@ -207,15 +235,15 @@ static int ceil_log2(int64_t v) {
 
 int tiles_plan(int64_t rows, int64_t cols, int num_cu, int rbits_hint, int cbits_hint, TilePlan* t) {
   int rb = rbits_hint;
-  if (rb <= 0) {  // about 2 chunks per CU, 32 .. 8192 rows (64 KiB of LDS: 2 workgroups of 8 waves per CU)
-    rb = 13;
-    while (rb > 5 && (rows >> rb) < 2 * (int64_t)num_cu) rb--;
+  if (rb <= 0) {  // 32 .. 1024-row chunks, about two workgroups of TW chunks per CU (64 KiB of LDS each)
+    rb = 10;
+    while (rb > 5 && (rows >> rb) < 2 * TW * (int64_t)num_cu) rb--;
   }
   int cb = cbits_hint > 0 ? cbits_hint : 18;  // 1 MiB FP32 slices of x (measured best of 2^18 / 2^19)
   const int lc = ceil_log2(cols);
   if (cb > lc) cb = lc > 0 ? lc : 1;
   if (cb < lc - 14) cb = lc - 14;  // at most 16384 slices (tile_count_kernel's LDS histogram)
-  if (rb < 1 || rb > 13 || cb < 1 || rb + cb > 32) return -1;
+  if (rb < 1 || rb > kMaxRowBits || cb < 1 || rb + cb > 32) return -1;
   t->rbits = rb;
   t->cbits = cb;
   t->nchunks = (rows + ((int64_t)1 << rb) - 1) >> rb;
@@ -248,13 +276,22 @@ int spmv_tiles_launch(const TilePlan& t, const int64_t* tptr, const uint32_t* ke
                       hipStream_t s) {
   if (nch <= 0) return 0;
   if (c0 < 0 || c0 + nch > t.nchunks) return TSVD_ERR_INTERNAL;
-  const size_t lds = ((size_t)1 << t.rbits) * 8;
+  const size_t lds = ((size_t)TW << t.rbits) * 8;
+  const unsigned grid = (unsigned)((nch + TW - 1) / TW);
+  static bool attr_set = false;  // up to 128 KiB of dynamic LDS for 2^11-row chunks
+  if (!attr_set) {
+    TSVD_HIP_TRY(hipFuncSetAttribute((const void*)spmv_tiles_kernel<float>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)((size_t)TW << kMaxRowBits) * 8));
+    TSVD_HIP_TRY(hipFuncSetAttribute((const void*)spmv_tiles_kernel<double>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)((size_t)TW << kMaxRowBits) * 8));
+    attr_set = true;
+  }
   if (x_is_f64)
-    hipLaunchKernelGGL((spmv_tiles_kernel<double>), dim3((unsigned)nch), dim3(TW * 64), lds, s, tptr, key, val, rows,
-                       t.rbits, t.cbits, t.nslices, (const double*)x, y, yf, base, c0);
+    hipLaunchKernelGGL((spmv_tiles_kernel<double>), dim3(grid), dim3(TW * 64), lds, s, tptr, key, val, rows, t.rbits,
+                       t.cbits, t.nslices, (const double*)x, y, yf, base, c0, nch);
   else
-    hipLaunchKernelGGL((spmv_tiles_kernel<float>), dim3((unsigned)nch), dim3(TW * 64), lds, s, tptr, key, val, rows,
-                       t.rbits, t.cbits, t.nslices, (const float*)x, y, yf, base, c0);
+    hipLaunchKernelGGL((spmv_tiles_kernel<float>), dim3(grid), dim3(TW * 64), lds, s, tptr, key, val, rows, t.rbits,
+                       t.cbits, t.nslices, (const float*)x, y, yf, base, c0, nch);
   TSVD_HIP_TRY(hipGetLastError());
   return 0;
 }

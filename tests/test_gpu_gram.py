@@ -112,7 +112,7 @@ def test_tuning_rejects_bad_values(ctx):
     with pytest.raises(P.TsvdError):
         P.set_tuning(ctx, group_kchunk=16)
     with pytest.raises(P.TsvdError):
-        P.set_tuning(ctx, sparse_row_bits=14)
+        P.set_tuning(ctx, sparse_row_bits=12)
     with pytest.raises(P.TsvdError):
-        P.set_tuning(ctx, sparse_row_bits=13, sparse_col_bits=20)
+        P.set_tuning(ctx, sparse_row_bits=11, sparse_col_bits=22)
     assert P.get_tuning(ctx) == {f: 0 for f in P.TUNING_FIELDS}

@@ -80,7 +80,7 @@ def awkward_csr(m=500, n=700, seed=11):
     return rp, ci, va, M
 
 
-@pytest.mark.parametrize("bits", [(4, 6), (1, 1), (0, 0), (13, 19)])
+@pytest.mark.parametrize("bits", [(4, 6), (1, 1), (0, 0), (11, 19)])
 def test_tiled_products_awkward_matrix(ctx, bits):
     """Both products of the sliced-tile kernels (tiny tiles put one row's
     entries across many tiles and many 64-entry chunks) against FP64 SciPy;
@@ -167,7 +167,7 @@ def test_sparse_trajectory_vs_oracle(ctx, m, n):
 
 def test_sparse_trajectory_many_tiles_vs_oracle(ctx):
     """The library's default tiling at a size where it spans many row chunks
-    (2^11-row chunks, 538 of them) and five column slices (2^18 columns each,
+    (2^8-row chunks, 4,297 of them) and five column slices (2^18 columns each,
     the last ragged): m = n = 1.1e6 with Poisson(50) uniform columns per row
     (draw order, repeats kept), k = 4 triplets of 20 fixed iterations each,
     against the implicit oracle on the same matrix (Eq. 2 in factored form,
