@@ -25,6 +25,7 @@
 // Team sizes and Gram chunking depend on the request alone, so each result is
 // the same alone and in any mix.
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -280,15 +281,16 @@ void launch(tsvd_server* s) {
     }
   if (!L) return;
   // CUs no running power launch holds.  Beside a running batch, a new one
-  // launches only once at least half the chip is free (a batch's grid is
-  // fixed at launch: started into a small remainder, its teams would queue on
-  // few CUs long after the running batch has ended).  It takes admitted
+  // launches only once 7/8 of the chip is free (a batch's grid is fixed at
+  // launch: started into a small remainder, its teams would queue on few CUs
+  // long after the running batch has ended; at the serving mix, two lanes gave
+  // p50 196 / 179 / 164 / 155 ms with 4/8 .. 7/8 free, one lane 115 ms).  It takes admitted
   // requests in arrival order while their teams fit those CUs, and stops at
   // the first that does not (a request with a large team is not overtaken
   // indefinitely: it waits at the head until enough CUs are released).
   int free_cus = s->ctx->num_cu;
   for (const Lane& l : s->lanes) free_cus -= l.live();
-  if (free_cus <= 0 || (s->busy_lanes() > 0 && 2 * free_cus < s->ctx->num_cu)) return;
+  if (free_cus <= 0 || (s->busy_lanes() > 0 && 8 * free_cus < 7 * s->ctx->num_cu)) return;
   const int maxb = s->cfg.max_batch;
   std::vector<uint64_t> take;
   for (size_t i = 0; i < s->admitted.size() && (int)take.size() < maxb; i++) {
