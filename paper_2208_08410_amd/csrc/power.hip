@@ -177,6 +177,81 @@ __device__ __forceinline__ void gemv_regrows(const RegRows<BT, NV, RR>& R, int c
   }
 }
 
+// One pass over the iterate for all of a wave's resident rows, FP32 B: the
+// RR register rows (cr + wave + 4q) and LR LDS rows (wave + 4j) of the block.
+// Each 4-column chunk of x is read from LDS once per wave and feeds every row;
+// the chunks of x and of the LDS rows are fetched two steps ahead, so a single
+// wave per SIMD is not left waiting on LDS latency step by step.  Requires
+// cr == 4 LR, nreg == 4 RR (or RR == 0) and ldsB == 256 NV (no ragged
+// chunk).  Every row is summed exactly as gemv_rows / gemv_regrows sum it (one
+// FMA chain per component over ascending chunks, then the components and the
+// lanes in FP64), so the result is the same bit for bit.
+template <int NV, int RR, int LR>
+__device__ __forceinline__ void gemv_fused(const RegRows<float, NV, RR>& R, const float* Bs, int ldsB, int cr,
+                                           const float* xs, double scale, double* yout) {
+  constexpr int NRR = RR > 0 ? RR : 0;
+  constexpr int D = 2;  // prefetch distance (chunks)
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const float* xp = xs + 4 * lane;
+  const float* lp[LR];
+#pragma unroll
+  for (int j = 0; j < LR; j++) lp[j] = Bs + (wave + 4 * j) * ldsB + 4 * lane;
+  float acc[NRR + LR][4];
+#pragma unroll
+  for (int q = 0; q < NRR + LR; q++)
+#pragma unroll
+    for (int e = 0; e < 4; e++) acc[q][e] = 0.0f;
+  float4 xb[D], lb[D][LR];
+#pragma unroll
+  for (int t = 0; t < D; t++) {
+    xb[t] = *(const float4*)(xp + 256 * t);
+#pragma unroll
+    for (int j = 0; j < LR; j++) lb[t][j] = *(const float4*)(lp[j] + 256 * t);
+  }
+#pragma unroll
+  for (int sidx = 0; sidx < NV; sidx++) {
+    const int slot = sidx % D;
+    const float4 xv = xb[slot];
+    float4 lv[LR];
+#pragma unroll
+    for (int j = 0; j < LR; j++) lv[j] = lb[slot][j];
+    if (sidx + D < NV) {
+      xb[slot] = *(const float4*)(xp + 256 * (sidx + D));
+#pragma unroll
+      for (int j = 0; j < LR; j++) lb[slot][j] = *(const float4*)(lp[j] + 256 * (sidx + D));
+    }
+    const float x4[4] = {xv.x, xv.y, xv.z, xv.w};
+    if constexpr (RR > 0) {
+#pragma unroll
+      for (int q = 0; q < RR; q++)
+#pragma unroll
+        for (int e = 0; e < 4; e++) acc[q][e] = fma(R.v[q][sidx][e], x4[e], acc[q][e]);
+    }
+#pragma unroll
+    for (int j = 0; j < LR; j++) {
+      acc[NRR + j][0] = fma(lv[j].x, xv.x, acc[NRR + j][0]);
+      acc[NRR + j][1] = fma(lv[j].y, xv.y, acc[NRR + j][1]);
+      acc[NRR + j][2] = fma(lv[j].z, xv.z, acc[NRR + j][2]);
+      acc[NRR + j][3] = fma(lv[j].w, xv.w, acc[NRR + j][3]);
+    }
+  }
+  double t[NRR + LR];
+#pragma unroll
+  for (int q = 0; q < NRR + LR; q++) {
+    t[q] = 0.0;
+#pragma unroll
+    for (int e = 0; e < 4; e++) t[q] += (double)acc[q][e];
+  }
+#pragma unroll
+  for (int q = 0; q < NRR + LR; q++) t[q] = wave_sum(t[q]);
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < NRR; q++) yout[cr + wave + 4 * q] = t[q] * scale;
+#pragma unroll
+    for (int j = 0; j < LR; j++) yout[wave + 4 * j] = t[NRR + j] * scale;
+  }
+}
+
 // Sum vals[0..P) over all G workgroups (published in the partial buffer under
 // epoch ex); out[0..P) receives the totals, identical in every workgroup.
 // Returns false (uniformly in the block) if a wait ran out of budget.
@@ -377,6 +452,12 @@ __device__ __forceinline__ int solve_problem(const PowerArgs& a, int b, int G, u
   const int cr = min(a.cache_rows, nrows);
   const int nreg = (RR > 0 && NV > 0) ? min(4 * RR, nrows - cr) : 0;
   const int g0 = cr + nreg;
+  // the single-pass product serves the common shapes: FP32 B, every chunk of x
+  // full, 4 or 8 LDS rows and all register rows present
+  int fused = 0;
+  if constexpr (sizeof(BT) == 4 && RR > 0 && NV > 0) {
+    if (a.ldsB == 256 * NV && nreg == 4 * RR && (cr == 4 || cr == 8)) fused = cr / 4;
+  }
 
   // one-time loads
   for (int li = 0; li < a.cache_rows; li++)
@@ -417,8 +498,15 @@ __device__ __forceinline__ int solve_problem(const PowerArgs& a, int b, int G, u
     double scale = 1.0;
     while (true) {
       // ---- y = B x on the block's rows
-      gemv_regrows<BT, NV, RR>(R, cr, nreg, xs, scale, yv);
-      gemv_range<BT, 4>(Bs, a.ldsB, 0, cr, xs, d, true, scale, yv);
+      bool one_pass = false;
+      if constexpr (sizeof(BT) == 4 && RR > 0 && NV > 0) {
+        if (fused == 2) { gemv_fused<NV, RR, 2>(R, Bs, a.ldsB, cr, xs, scale, yv); one_pass = true; }
+        else if (fused == 1) { gemv_fused<NV, RR, 1>(R, Bs, a.ldsB, cr, xs, scale, yv); one_pass = true; }
+      }
+      if (!one_pass) {
+        gemv_regrows<BT, NV, RR>(R, cr, nreg, xs, scale, yv);
+        gemv_range<BT, 4>(Bs, a.ldsB, 0, cr, xs, d, true, scale, yv);
+      }
       gemv_range<BT, (RR > 0 ? 2 : 8)>(Bg, a.ldb, g0, nrows, xs, d, a.vec_ok != 0, scale, yv);
       __syncthreads();
       it++;
