@@ -188,6 +188,10 @@ static double* noalloc_scratch(int device) {
   return g_scratch_ptr[device];
 }
 
+namespace {
+bool ws_fits(tsvd_ctx* ctx, size_t need, int64_t budget);  // below
+}  // namespace
+
 extern "C" {
 
 tsvd_status tsvd_ctx_create(int device, tsvd_ctx** out) {
@@ -255,7 +259,11 @@ tsvd_status tsvd_gram_dense(tsvd_ctx* ctx, const void* A, int32_t dtype, int64_t
   if (st) return st;
   hipSetDevice(ctx->device);
   SyrkPlan sp;
-  syrk_plan(mode, d, K, rows_per_block, ctx->num_cu, &sp, ctx->tuning.gram_tile, ctx->tuning.gram_chunks);
+  syrk_plan(mode, d, K, rows_per_block, ctx->num_cu, &sp, ctx->tuning.gram_tile, ctx->tuning.gram_chunks, 1);
+  // the BF16 planes of the two-pass form need 4 B per element of A on top of
+  // the partial tiles; without room for them the one-pass kernel runs
+  if (sp.packed && !ws_fits(ctx, align256(sp.partial_bytes), 0))
+    syrk_plan(mode, d, K, rows_per_block, ctx->num_cu, &sp, ctx->tuning.gram_tile, ctx->tuning.gram_chunks, 0);
   st = ensure_ws(ctx, align256(sp.partial_bytes), 0);
   if (st) return st;
   int rc = syrk_launch(mode, side, A, m, n, lda, sp, ctx->ws, B, ldb, accumulate, (hipStream_t)stream);
@@ -855,12 +863,17 @@ tsvd_status tsvd_dense(tsvd_ctx* ctx, const void* A, int32_t dtype, int32_t loc,
   const int64_t ldb = (d + 3) & ~3;
 
   SyrkPlan sp;
-  syrk_plan(mode, d, K, o->rows_per_block, ctx->num_cu, &sp, ctx->tuning.gram_tile, ctx->tuning.gram_chunks);
+  syrk_plan(mode, d, K, o->rows_per_block, ctx->num_cu, &sp, ctx->tuning.gram_tile, ctx->tuning.gram_chunks, 1);
   PowerPlan pp;
   const bool onchip = plan_onchip(ctx, eb, d, k, &pp);
   const size_t b_bytes = align256((size_t)d * ldb * eb);
   const size_t fin_bytes = align256((size_t)finish_workspace_doubles(m, n, side, k) * 8);
-  const size_t need = b_bytes + align256(sp.partial_bytes) + phase_ws_bytes(onchip, pp, d, k) + fin_bytes + 4096;
+  size_t need = b_bytes + align256(sp.partial_bytes) + phase_ws_bytes(onchip, pp, d, k) + fin_bytes + 4096;
+  if (sp.packed && !ws_fits(ctx, need, o->hbm_budget)) {
+    // no room for the BF16 planes of the two-pass Gram: the one-pass kernel
+    syrk_plan(mode, d, K, o->rows_per_block, ctx->num_cu, &sp, ctx->tuning.gram_tile, ctx->tuning.gram_chunks, 0);
+    need = b_bytes + align256(sp.partial_bytes) + phase_ws_bytes(onchip, pp, d, k) + fin_bytes + 4096;
+  }
   if (auto_method && !ws_fits(ctx, need, o->hbm_budget))
     return dense_implicit(ctx, A, dtype, loc, m, n, lda, o, k, U, ldu, S, V, ldv, info, stream);
   st = ensure_ws(ctx, need, o->hbm_budget);

@@ -13,10 +13,15 @@ enum { MODE_FP64 = 0, MODE_FP32 = 1, MODE_BF16X3 = 2 };
 struct SyrkPlan {
   int BM, nt, T, S, xcd_map;
   int64_t kchunk, partial_elems;
-  size_t partial_bytes;
+  size_t partial_bytes;   // workspace of the launch: partial tiles (+ the BF16 planes when packed)
+  int packed;             // BF16X3, 256-wide tiles: split pass into k-packed planes, then direct-to-LDS tiles
+  int64_t dp, Kp;         // packed: Gram dimension and contraction length padded (256, 32)
+  size_t plane_off;       // packed: byte offset of the hi plane in the workspace
 };
+// packed_ok: the two-pass BF16X3 form may be chosen (A resident in HBM and
+// room for 4 B per element of planes)
 int syrk_plan(int mode, int64_t d, int64_t K, int64_t rows_per_block, int num_cu, SyrkPlan* p, int tile = 0,
-              int chunks = 0);
+              int chunks = 0, int packed_ok = 0);
 int syrk_launch(int mode, int side, const void* A, int64_t m, int64_t n, int64_t lda, const SyrkPlan& p,
                 void* partial, void* B, int64_t ldb, int accumulate, hipStream_t stream);
 

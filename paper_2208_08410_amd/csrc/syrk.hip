@@ -607,6 +607,212 @@ __global__ __launch_bounds__(512, 1) void syrk_bf16x3_big_kernel(SyrkArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// BF16X3 Gram of 256-wide tiles over an A resident in HBM, in two passes.
+// Pass 1 (split_pack_kernel) reads A once and writes its hi and lo parts as
+// two BF16 planes in a k-packed layout: plane[g * dp + c] is the 16-byte chunk
+// of the 8 contraction indices 8g .. 8g + 7 of Gram index c, zero beyond K and
+// d, so the planes need no bounds checks.  Pass 2 (syrk_packed_kernel) loads
+// those chunks straight into LDS with global_load_lds_dwordx4 (no register
+// staging and no split in its loop), four 16-wide k-stages ahead.  The LDS
+// layout of a stage is the planes' layout, which is also what an MFMA lane
+// reads: 8 consecutive k of one row in one 16-byte load, 32 rows of one
+// 16-byte group contiguous (conflict-free).  Per 16 k the tile takes the big
+// kernel's products in the big kernel's order, so its partial tiles are the
+// same bits.
+// ---------------------------------------------------------------------------
+constexpr int PK_BK = 16, PK_NS = 4;                           // k per stage, stages in flight
+constexpr int PK_BUF = (PK_BK / 8) * BIG_BM * 16;              // one plane of one panel per stage (8 KB)
+constexpr int PK_STAGE = 4 * PK_BUF;                           // I hi, I lo, J hi, J lo
+constexpr size_t PK_LDS = (size_t)PK_NS * PK_STAGE;            // 128 KB
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) void glb_void_t;
+
+template <int SIDE>
+__global__ __launch_bounds__(256) void split_pack_kernel(const float* A, int64_t lda, int64_t d, int64_t K, int64_t dp,
+                                                         int64_t ng, int vec_ok, bf16x8* H, bf16x8* L) {
+  const int64_t t = blockIdx.x * 256ll + threadIdx.x;
+  if (SIDE == 0) {
+    // rows k of A are the contraction: a thread splits 4 columns of 8 rows
+    const int64_t nc4 = dp / 4;
+    if (t >= ng * nc4) return;
+    const int64_t g = t / nc4, c = 4 * (t % nc4);
+    float v[8][4];
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
+      const int64_t k = 8 * g + e;
+      const float* p = A + k * lda + c;
+      if (k < K && vec_ok && c + 3 < d) {
+        const float4 f = *(const float4*)p;
+        v[e][0] = f.x; v[e][1] = f.y; v[e][2] = f.z; v[e][3] = f.w;
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; i++) v[e][i] = (k < K && c + i < d) ? p[i] : 0.0f;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      bf16x8 h, l;
+#pragma unroll
+      for (int e = 0; e < 8; e++) { __bf16 x, y; split_bf16(v[e][i], x, y); h[e] = x; l[e] = y; }
+      H[g * dp + c + i] = h;
+      L[g * dp + c + i] = l;
+    }
+  } else {
+    // columns of A are the contraction: a thread splits 4 groups of 8 of one row
+    const int64_t ng4 = (ng + 3) / 4;
+    if (t >= ng4 * dp) return;
+    const int64_t c = t % dp, g0 = 4 * (t / dp);
+#pragma unroll
+    for (int gi = 0; gi < 4; gi++) {
+      const int64_t g = g0 + gi;
+      if (g >= ng) break;
+      float v[8];
+      const float* p = A + c * lda + 8 * g;
+      if (c < d && vec_ok && 8 * g + 7 < K) {
+        const float4 f0 = *(const float4*)p, f1 = *(const float4*)(p + 4);
+        v[0] = f0.x; v[1] = f0.y; v[2] = f0.z; v[3] = f0.w; v[4] = f1.x; v[5] = f1.y; v[6] = f1.z; v[7] = f1.w;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; e++) v[e] = (c < d && 8 * g + e < K) ? p[e] : 0.0f;
+      }
+      bf16x8 h, l;
+#pragma unroll
+      for (int e = 0; e < 8; e++) { __bf16 x, y; split_bf16(v[e], x, y); h[e] = x; l[e] = y; }
+      H[g * dp + c] = h;
+      L[g * dp + c] = l;
+    }
+  }
+}
+
+struct PackArgs {
+  const bf16x8* H;
+  const bf16x8* L;
+  int64_t dp, Kp, kchunk;
+  int nt, T, S, xcd_map;
+  float* partial;
+};
+
+// s_waitcnt vmcnt(N) alone (the other counters at their maxima)
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | 0x70 | 0xF00);
+}
+// keeps the compiler from moving memory operations across the hardware barrier
+__device__ __forceinline__ void compiler_fence() { asm volatile("" ::: "memory"); }
+
+template <bool DIAG>
+__device__ __forceinline__ void packed_tile(const PackArgs& a, unsigned char* smem, int s, int ti, int tj) {
+  constexpr int NBUF = DIAG ? 2 : 4;                 // a diagonal tile needs panel I only
+  constexpr int IPB = (PK_BK / 8) * BIG_BM / 64;     // wave-loads per buffer and stage
+  constexpr int LPW = NBUF * IPB / 8;                // per wave and stage
+  static_assert(NBUF * IPB % 8 == 0, "loads per wave");
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wm = wave >> 2, wn = wave & 3;           // 2 x 4 waves, each 128 x 64
+  const int64_t k0 = (int64_t)s * a.kchunk;
+  const int64_t kend = k0 + a.kchunk < a.Kp ? k0 + a.kchunk : a.Kp;
+  const int nk = (int)((kend - k0) / PK_BK);
+  const int64_t cI = (int64_t)ti * BIG_BM, cJ = (int64_t)tj * BIG_BM;
+
+  // stage kt into LDS slot `slot`: wave-load u covers 64 consecutive chunks
+  // (one 1 KB run in the plane and in LDS; lane i lands at offset 16 i)
+  auto issue = [&](int kt, int slot) {
+    const int64_t gb = (k0 + (int64_t)kt * PK_BK) / 8;
+#pragma unroll
+    for (int i = 0; i < LPW; i++) {
+      const int u = wave * LPW + i;
+      const int b = u / IPB, r = u % IPB;
+      const int q = r * 64 + lane;
+      const int g = q / BIG_BM, c = q % BIG_BM;
+      const bf16x8* src = ((b & 1) ? a.L : a.H) + (gb + g) * a.dp + ((b < 2) ? cI : cJ) + c;
+      unsigned char* dst = smem + slot * PK_STAGE + b * PK_BUF + r * 1024;
+      __builtin_amdgcn_global_load_lds((glb_void_t*)src, (lds_void_t*)dst, 16, 0, 0);
+    }
+  };
+
+  floatx16 acc[4][2];
+#pragma unroll
+  for (int i = 0; i < 4; i++)
+#pragma unroll
+    for (int j = 0; j < 2; j++)
+#pragma unroll
+      for (int e = 0; e < 16; e++) acc[i][j][e] = 0.0f;
+
+#pragma unroll
+  for (int st = 0; st < PK_NS - 1; st++)
+    if (st < nk) issue(st, st);
+  for (int kt = 0; kt < nk; kt++) {
+    // this wave's loads of stage kt are done once at most the later stages'
+    // are outstanding; the barrier then makes every wave's visible, and every
+    // wave is past its reads of the slot refilled below
+    if (kt + PK_NS - 2 < nk) wait_vmcnt<LPW * (PK_NS - 2)>();
+    else wait_vmcnt<0>();
+    compiler_fence();
+    __builtin_amdgcn_s_barrier();
+    compiler_fence();
+    if (kt + PK_NS - 1 < nk) issue(kt + PK_NS - 1, (kt + PK_NS - 1) % PK_NS);
+    const unsigned char* base = smem + (kt % PK_NS) * PK_STAGE;
+    const __bf16* Ih = (const __bf16*)base;
+    const __bf16* Il = (const __bf16*)(base + PK_BUF);
+    const __bf16* Jh = DIAG ? Ih : (const __bf16*)(base + 2 * PK_BUF);
+    const __bf16* Jl = DIAG ? Il : (const __bf16*)(base + 3 * PK_BUF);
+    const int g = lane >> 5;
+    bf16x8 ah[4], al[4], bh[2], bl[2];
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      const int r = wm * 128 + i * 32 + (lane & 31);
+      ah[i] = *(const bf16x8*)(Ih + (g * BIG_BM + r) * 8);
+      al[i] = *(const bf16x8*)(Il + (g * BIG_BM + r) * 8);
+    }
+#pragma unroll
+    for (int j = 0; j < 2; j++) {
+      const int c = wn * 64 + j * 32 + (lane & 31);
+      bh[j] = *(const bf16x8*)(Jh + (g * BIG_BM + c) * 8);
+      bl[j] = *(const bf16x8*)(Jl + (g * BIG_BM + c) * 8);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+      for (int j = 0; j < 2; j++) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+      }
+  }
+  wait_vmcnt<0>();  // no load into LDS may outlive the workgroup
+  float* out = a.partial + ((int64_t)s * a.T + (ti * (ti + 1) / 2 + tj)) * BIG_BM * BIG_BM;
+#pragma unroll
+  for (int i = 0; i < 4; i++)
+#pragma unroll
+    for (int j = 0; j < 2; j++)
+#pragma unroll
+      for (int e = 0; e < 16; e++) {
+        const int r = wm * 128 + i * 32 + (e >> 2) * 8 + (lane >> 5) * 4 + (e & 3);
+        const int c = wn * 64 + j * 32 + (lane & 31);
+        out[r * BIG_BM + c] = acc[i][j][e];
+      }
+}
+
+__global__ __launch_bounds__(512, 1) void syrk_packed_kernel(PackArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  int s, t;
+  if (a.xcd_map) {
+    const int x = blockIdx.x & 7, local = blockIdx.x >> 3;
+    s = x + 8 * (local / a.T);
+    t = local % a.T;
+  } else {
+    s = blockIdx.x / a.T;
+    t = blockIdx.x % a.T;
+  }
+  int ti, tj;
+  tri_tile(t, ti, tj);
+  if (ti == tj) packed_tile<true>(a, smem, s, ti, tj);
+  else packed_tile<false>(a, smem, s, ti, tj);
+}
+
+// ---------------------------------------------------------------------------
 // Reduction of chunk partials into the full symmetric B.
 // One workgroup per 32x32 sub-tile of a triangle tile; sums the S partials in
 // chunk order, then writes the sub-tile and (through LDS) its transpose, both
@@ -722,7 +928,7 @@ int syrk_grouped_launch(int mode, int side, const GramJob* d_jobs, int njobs, in
 // Host launchers
 // ---------------------------------------------------------------------------
 int syrk_plan(int mode, int64_t d, int64_t K, int64_t rows_per_block, int num_cu, SyrkPlan* p, int tile,
-              int chunks) {
+              int chunks, int packed_ok) {
   // BF16X3 uses 256-wide tiles for large Grams unless told otherwise
   if (mode == MODE_BF16X3 && tile == 0) tile = d >= 1024 ? 256 : 128;
   const int BM = (mode == MODE_FP64) ? 64 : (mode == MODE_BF16X3 && tile == 256 ? 256 : 128);
@@ -769,6 +975,18 @@ int syrk_plan(int mode, int64_t d, int64_t K, int64_t rows_per_block, int num_cu
   p->xcd_map = (p->S % 8 == 0) ? 1 : 0;
   p->partial_elems = (int64_t)p->S * p->T * BM * BM;
   p->partial_bytes = (size_t)p->partial_elems * (mode == MODE_FP64 ? 8 : 4);
+  p->packed = 0;
+  p->dp = p->Kp = 0;
+  p->plane_off = 0;
+  if (packed_ok && mode == MODE_BF16X3 && BM == 256 && rows_per_block <= 0 && K > 0) {
+    // the chunks end on 32-row boundaries and the last one starts below K, so
+    // every stage of every chunk lies inside the planes' Kp rows
+    p->packed = 1;
+    p->dp = (int64_t)p->nt * BIG_BM;
+    p->Kp = ((K + 31) / 32) * 32;
+    p->plane_off = (p->partial_bytes + 255) & ~(size_t)255;
+    p->partial_bytes = p->plane_off + (size_t)4 * p->Kp * p->dp;  // hi and lo, 2 B each
+  }
   return 0;
 }
 
@@ -782,7 +1000,21 @@ int syrk_launch(int mode, int side, const void* A, int64_t m, int64_t n, int64_t
   a.vec_ok = (((uintptr_t)A & 15) == 0) && (lda % 4 == 0);
   a.partial = partial;
   const int grid = p.T * p.S;
-  if (mode == MODE_BF16X3 && p.BM == 256) {
+  if (p.packed) {
+    const int64_t ng = p.Kp / 8;
+    bf16x8* H = (bf16x8*)((char*)partial + p.plane_off);
+    bf16x8* L = H + ng * p.dp;
+    const int64_t nthr = side == 0 ? ng * (p.dp / 4) : ((ng + 3) / 4) * p.dp;
+    const dim3 sg((unsigned)((nthr + 255) / 256));
+    if (side == 0) hipLaunchKernelGGL((split_pack_kernel<0>), sg, dim3(256), 0, stream, (const float*)A, lda, a.d, a.K, p.dp, ng, a.vec_ok, H, L);
+    else hipLaunchKernelGGL((split_pack_kernel<1>), sg, dim3(256), 0, stream, (const float*)A, lda, a.d, a.K, p.dp, ng, a.vec_ok, H, L);
+    TSVD_HIP_TRY(hipGetLastError());
+    PackArgs pa;
+    pa.H = H; pa.L = L; pa.dp = p.dp; pa.Kp = p.Kp; pa.kchunk = p.kchunk;
+    pa.nt = p.nt; pa.T = p.T; pa.S = p.S; pa.xcd_map = p.xcd_map; pa.partial = (float*)partial;
+    TSVD_HIP_TRY(hipFuncSetAttribute((const void*)syrk_packed_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)PK_LDS));
+    hipLaunchKernelGGL(syrk_packed_kernel, dim3(grid), dim3(512), PK_LDS, stream, pa);
+  } else if (mode == MODE_BF16X3 && p.BM == 256) {
     const void* fn = side == 0 ? (const void*)syrk_bf16x3_big_kernel<0> : (const void*)syrk_bf16x3_big_kernel<1>;
     TSVD_HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)BIG_LDS));
     if (side == 0) hipLaunchKernelGGL((syrk_bf16x3_big_kernel<0>), dim3(grid), dim3(512), BIG_LDS, stream, a);
