@@ -827,7 +827,9 @@ def main():
     bm = 256 if (a.gram == "bf16x3" and a.n >= 1024) else 128
     nt = (a.n + bm - 1) // bm
     gram_flops_hw = (3 if a.gram == "bf16x3" else 1) * 2.0 * a.m * (nt * (nt + 1) // 2) * bm * bm
-    gram_kernel = ("syrk_bf16x3_big_kernel<0> + syrk_reduce_kernel<float,256>" if bm == 256 else
+    # A resident in HBM: 256-wide BF16X3 Grams take the two-pass form (split into
+    # BF16 planes, then the direct-to-LDS tile kernel) whenever the planes fit
+    gram_kernel = ("split_pack_kernel<0> + syrk_packed_kernel + syrk_reduce_kernel<float,256>" if bm == 256 else
                    "syrk_partial_kernel<%s,0> + syrk_reduce_kernel<float,128>" % a.gram)
     c2_shape = a.n == 4096 and a.m == 200000 and a.k == 64
     gram_flops_alg = 1.0 * a.m * a.n * (a.n + 1)
@@ -839,7 +841,7 @@ def main():
         "peak": gram_peak,
         "unit": "TFLOP/s",
         "frac": gram_flops_hw / (t_gram * 1e-3) / 1e12 / gram_peak,
-        "traffic": measured_traffic("syrk_bf16x3_big_kernel<0>+syrk_reduce_kernel<float,256>")
+        "traffic": measured_traffic("split_pack_kernel<0>+syrk_packed_kernel+syrk_reduce_kernel<float,256>")
         if (c2_shape and bm == 256) else None,
         "traffic_note": "HBM bytes per launch pair from profiles/traffic_*.txt; A alone is m*n*4 bytes",
         "effective_fp32_equiv_tflops": gram_flops_alg / (t_gram * 1e-3) / 1e12,
