@@ -299,8 +299,9 @@ def request_pool(a, dev, loc):
 
 def batch_main(a):
     """Batched workload: a fixed batch of problems from the serving mix, solved
-    by one tsvd_dense_batched call per step (grouped Gram, power teams formed on
-    the fly, grouped finish), A resident in HBM."""
+    by one tsvd_dense_batched call per step (one engine launch over Gram units,
+    tile reductions and power-team seats, then the grouped finish), A resident
+    in HBM."""
     import numpy as np
     import torch
 

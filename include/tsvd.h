@@ -155,8 +155,8 @@ typedef struct {
   int32_t gram_tile;     /* BF16X3 Gram tile edge: 0 (library choice), 128 or 256 */
   int32_t gram_chunks;   /* contraction chunks (split-K) per Gram launch: 0 = library choice */
   int32_t power_blocks;  /* workgroups of the power-iteration launch: 0 = one per CU; for batches the cap
-                            on every team and on the power launch's grid */
-  int32_t team_kib;      /* batched power launch: KiB of a problem's Gram per team workgroup, which
+                            on every team and on the engine launch's grid */
+  int32_t team_kib;      /* batched engine launch: KiB of a problem's Gram per team workgroup, which
                             sets the team size (ceil(4 d^2 / (team_kib * 1024)) workgroups);
                             0 = 256; range [8, 65536] */
   int32_t group_kchunk;  /* batched Gram: contraction rows per work unit; 0 = 2048; range [32, 2^20] */
@@ -259,17 +259,20 @@ typedef struct {
   int64_t ldv;
 } tsvd_problem;
 
-/* Algorithm 1 for `count` independent problems of any mix of shapes, in three
- * grouped launches: the Gram of every problem (work units = problem x split-K
- * chunk x triangle tile, Algorithm 3's block products), one persistent power
- * launch in which workgroups form a team per problem as they come free (the
- * problems wait in a queue, longest first; a team runs Algorithm 2 with
- * deflation on its problem, then its members return to the queue), and the
- * FP64 finishing product.  Each
- * problem's result is what tsvd_dense computes for it, up to the rounding of a
- * different reduction order.  hbm_budget bounds the workspace of the whole
- * batch (0 = no limit).  infos (optional, count entries) receive per-problem
- * k_done, converged, iters, lambda and the batch's phase times; statuses
+/* Algorithm 1 for `count` independent problems of any mix of shapes.  One
+ * persistent engine launch takes work items from one list in order: per
+ * problem (queued longest first) its Gram units (problem x split-K chunk x
+ * triangle tile, Algorithm 3's block products), the reduction of each tile's
+ * chunk partials into the problem's B, and the seats of its power team (a
+ * team runs Algorithm 2 with deflation on its problem, then its members take
+ * further items), so later problems' Gram work runs beside earlier problems'
+ * teams; then one grouped FP64 finishing product.  Each problem's result is
+ * what tsvd_dense computes for it, up to the rounding of a different
+ * reduction order.  hbm_budget bounds the workspace of the whole batch (0 =
+ * no limit).  infos (optional, count entries) receive per-problem k_done,
+ * converged, iters, lambda and the batch's phase times (t_gram_ms covers only
+ * the clears before the engine launch, t_eig_ms the engine: Gram, reductions
+ * and power iterations together); statuses
  * (optional HOST array of count) receive per-problem statuses.  Synchronises
  * `stream`.  Returns OK when every problem is OK, else the status of the first
  * failing problem (argument errors are found before any launch). */
@@ -289,7 +292,7 @@ typedef struct {
   int32_t max_slots;       /* requests admitted and not yet completed, at most; 0 = 256 */
   int32_t max_batch;       /* requests per batch launch, at most; 0 = max_slots */
   int32_t lanes;           /* batches that may run on the device at once, 1..8; 0 = 1.  A further batch
-                              launches only into the CUs the running power launches have released, with
+                              launches only into the CUs the running engine launches have released, with
                               the requests whose team fits them, so all launches always fit the chip
                               together */
 } tsvd_server_config;
@@ -315,7 +318,7 @@ typedef struct {
  * (its Gram, split-K partials and finish sums, plus its A when A is in pinned
  * host memory, which is then copied at once on the copy stream); whenever a
  * lane is idle it launches admitted requests on it as one batch (as
- * tsvd_dense_batched) into the CUs that no running power launch holds (the
+ * tsvd_dense_batched) into the CUs that no running engine launch holds (the
  * launches' workgroups report their exit through pinned host memory), taking
  * the requests whose team fits; when a lane's batch completes it frees that
  * batch's memory and completes its tickets.  So a request that arrives while

@@ -30,16 +30,15 @@ struct BatchPlan {
   int count = 0;
   std::vector<ProbPlan> P;
   std::vector<int> queue;   // power queue: problem indices, longest first
-  int grid = 0;             // power workgroups
+  int grid = 0;             // engine workgroups
+  int nitems = 0;           // engine work items (Gram units, reductions, team seats)
   // batch workspace layout
-  size_t off_gjobs = 0, off_pargs = 0, off_order = 0, off_gsize = 0, off_fjobs = 0, desc_bytes = 0;
+  size_t off_gjobs = 0, off_pargs = 0, off_items = 0, off_fjobs = 0, desc_bytes = 0;
   size_t off_status = 0, off_iters = 0, off_lambda = 0, off_fixed = 0;
-  size_t off_zero = 0, zero_words = 0, off_sched = 0;  // cleared before the power launch
+  size_t off_zero = 0, zero_words = 0, off_ctr = 0;  // cleared by the engine launch
   size_t batch_ws_bytes = 0;
   size_t total_k = 0;
   // filled by batch_enqueue (host copies live until the stream completes)
-  struct Group { int mode, side, first, count; int64_t units, runits; };
-  std::vector<Group> ggroups;
   int fcount[2] = {0, 0};
   int64_t funits[2] = {0, 0}, fcols[2] = {0, 0};
   std::vector<char> desc_v;
@@ -54,16 +53,17 @@ struct BatchPlan {
 };
 
 // validate the problems and plan tiles, teams and workspace sizes; team_cap
-// (0 = the CU count) bounds every team and the power launch's grid
+// (0 = the CU count) bounds every team and the engine launch's grid
 tsvd_status batch_plan(tsvd_ctx* ctx, int count, const tsvd_problem* probs, BatchPlan& bp, int team_cap = 0);
 // enqueue the whole batch on `stream` (asynchronous).  bbase: batch workspace
 // (bp.batch_ws_bytes); pbase[i]: problem i's workspace (bp.P[i].ws_bytes).
-// ev (optional, 4 events) marks start / after Gram / after power / end.
+// ev (optional, 4 events) marks start / before the engine launch (the clears
+// done) / after it (Gram, reductions and power iterations) / end.
 // hpin (optional): pinned host memory of bp.host_bytes() for the descriptor
 // upload and the result readback, so that no copy waits on the host; without
 // it, pageable vectors are used.  The small results land in bp.hs / hit / hl
 // once the stream has completed.
-// exit_flags / exit_id: passed to the power launch (its workgroups report
+// exit_flags / exit_id: passed to the engine launch (its workgroups report
 // their exit there, for the server's CU accounting)
 tsvd_status batch_enqueue(tsvd_ctx* ctx, const tsvd_problem* probs, BatchPlan& bp, char* bbase, char* const* pbase,
                           hipStream_t stream, hipEvent_t* ev, char* hpin = nullptr, int* exit_flags = nullptr,

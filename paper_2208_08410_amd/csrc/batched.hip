@@ -1,15 +1,15 @@
-// Batched dense t-SVD: many independent problems of uneven shape in a few
-// grouped launches (Gram, power iteration, finishing product).
+// Batched dense t-SVD: many independent problems of uneven shape in one
+// engine launch (Gram, reduction, power iteration) and a grouped finish.
 //
 // The method per problem is the single-problem one (Algorithm 1 on the Gram
 // of Algorithm 2/3): only the scheduling differs.
-//   Gram:   one launch per (Gram mode, side) whose workgroups are the
-//           (problem, split-K chunk, 128x128 triangle tile) units of every
-//           problem, then one deterministic reduction launch.
-//   Power:  one persistent launch; workgroups form a team for each problem
-//           as they come free (problems queued longest first) and the team
-//           runs the single-problem body on it (a team is to one problem what
-//           the whole grid is to a single call).
+//   Engine: one persistent launch whose workgroups take work items from one
+//           list in order: per problem (queued longest first) its Gram units
+//           (split-K chunk x 128x128 triangle tile), the reduction of each
+//           tile's chunk partials into B, and the seats of its power team; a
+//           team runs the single-problem body (a team is to one problem what
+//           the whole grid is to a single call).  Later problems' Gram units
+//           run beside earlier problems' teams.
 //   Finish: one grouped FP64 product launch per side, then sigma and scale/sign.
 //
 // A problem's team size depends only on its own Gram dimension and the
@@ -99,8 +99,8 @@ tsvd_status batch_plan(tsvd_ctx* ctx, int count, const tsvd_problem* probs, Batc
     const int64_t M = p.right ? q.m : q.n;
     p.nb = (int)((M + 127) / 128);
     p.G = wanted_team(p.d, cap, team_kib);
-    // the batched kernel's own static LDS comes out of the per-workgroup budget
-    if (power_plan(4, (int)p.d, p.k, ctx->num_cu, ctx->max_lds - power_dyn_static_lds(), p.G, &p.pp))
+    // the engine kernel's own static LDS comes out of the per-workgroup budget
+    if (power_plan(4, (int)p.d, p.k, ctx->num_cu, ctx->max_lds - engine_static_lds(), p.G, &p.pp))
       return fail(ctx, TSVD_ERR_UNSUPPORTED, "problem %d: d=%lld too large for the LDS-resident iterate", i,
                   (long long)p.d);
     p.G = p.pp.G;
@@ -118,9 +118,13 @@ tsvd_status batch_plan(tsvd_ctx* ctx, int count, const tsvd_problem* probs, Batc
   std::stable_sort(bp.queue.begin(), bp.queue.end(), [&](int x, int y) {
     return team_cost(bp.P[x].d, bp.P[x].k, bp.P[x].G) > team_cost(bp.P[y].d, bp.P[y].k, bp.P[y].G);
   });
-  int64_t seats = 0;
-  for (auto& p : bp.P) seats += p.G;
-  bp.grid = (int)std::min<int64_t>(seats, cap);
+  // the engine runs on every CU the cap allows (the Gram units of the whole
+  // batch are spread over them; every team fits)
+  bp.grid = cap;
+  int64_t items = 0;
+  for (auto& p : bp.P) items += (int64_t)p.S * p.T + p.T + p.G;
+  if (items > (int64_t)1 << 30) return fail(ctx, TSVD_ERR_UNSUPPORTED, "batch too large (%lld work items)", (long long)items);
+  bp.nitems = (int)items;
 
   // batch-level workspace: descriptors, statuses and iteration logs, then the
   // cleared region (queue counters and every problem's exchange buffers)
@@ -128,8 +132,7 @@ tsvd_status batch_plan(tsvd_ctx* ctx, int count, const tsvd_problem* probs, Batc
   auto take = [&](size_t b) { off = align256(off); const size_t o2 = off; off += b; return o2; };
   bp.off_gjobs = take((size_t)count * sizeof(GramJob));
   bp.off_pargs = take((size_t)count * sizeof(PowerArgs));
-  bp.off_order = take((size_t)count * sizeof(int));
-  bp.off_gsize = take((size_t)count * sizeof(int));
+  bp.off_items = take((size_t)bp.nitems * sizeof(EngineItem));
   bp.off_fjobs = take((size_t)count * sizeof(FinishJob));
   bp.total_k = 0;
   for (auto& p : bp.P) bp.total_k += p.k;
@@ -139,7 +142,7 @@ tsvd_status batch_plan(tsvd_ctx* ctx, int count, const tsvd_problem* probs, Batc
   bp.off_iters = take(bp.total_k * sizeof(int));
   bp.off_lambda = take(bp.total_k * sizeof(double));
   bp.off_zero = align256(off);
-  bp.off_sched = take((size_t)(count + 1) * sizeof(int));
+  bp.off_ctr = take((size_t)(4 * count + 1) * sizeof(int));
   for (auto& p : bp.P) {
     const size_t dpad = (size_t)((p.d + 3) & ~3), pw = (size_t)2 * (p.k + 2);
     p.ex_words = 2 * dpad + 2 * (size_t)p.G * pw + 8 * dpad;  // x (2 parities), partials, v and w
@@ -181,41 +184,31 @@ tsvd_status batch_enqueue(tsvd_ctx* ctx, const tsvd_problem* probs, BatchPlan& b
     for (int i = 0; i < count; i++) { kofs[i] = ko; ko += bp.P[i].k; }
   }
 
-  // Gram jobs grouped by (mode, side): contiguous runs, one launch each
-  bp.ggroups.clear();
-  {
-    int gi = 0;
-    for (int mode : {MODE_BF16X3, MODE_FP32})
-      for (int side : {0, 1}) {
-        BatchPlan::Group g{mode, side, gi, 0, 0, 0};
-        for (int i = 0; i < count; i++) {
-          const ProbPlan& p = bp.P[i];
-          if (p.mode != mode || p.side != side) continue;
-          const tsvd_problem& q = probs[i];
-          GramJob& j = gj[gi++];
-          j.A = q.A; j.m = q.m; j.n = q.n; j.lda = q.lda; j.side = side;
-          j.nt = p.nt; j.T = p.T; j.S = p.S; j.kchunk = p.kchunk;
-          j.vec_ok = (((uintptr_t)q.A & 15) == 0) && (q.lda % 4 == 0);
-          j.partial = pbase[i] + p.off_partial;
-          j.B = pbase[i] + p.off_B;
-          j.ldb = p.ldb;
-          j.ubegin = g.units;
-          j.rbegin = g.runits;
-          g.units += (int64_t)p.S * p.T;
-          g.runits += (int64_t)16 * p.T;
-          g.count++;
-        }
-        if (g.count) bp.ggroups.push_back(g);
-      }
+  // one Gram job per problem (job i is problem i)
+  for (int i = 0; i < count; i++) {
+    const ProbPlan& p = bp.P[i];
+    const tsvd_problem& q = probs[i];
+    GramJob& j = gj[i];
+    j.A = q.A; j.m = q.m; j.n = q.n; j.lda = q.lda; j.side = p.side; j.mode = p.mode;
+    j.nt = p.nt; j.T = p.T; j.S = p.S; j.kchunk = p.kchunk;
+    j.vec_ok = (((uintptr_t)q.A & 15) == 0) && (q.lda % 4 == 0);
+    j.partial = pbase[i] + p.off_partial;
+    j.B = pbase[i] + p.off_B;
+    j.ldb = p.ldb;
   }
-  // power queue
+  // the engine's work list: per problem in power-queue order, its Gram units,
+  // its tile reductions, then the seats of its team
   {
-    int* ord = (int*)(h + bp.off_order);
-    int* gs = (int*)(h + bp.off_gsize);
-    for (int q = 0; q < count; q++) {
-      ord[q] = bp.queue[q];
-      gs[q] = bp.P[bp.queue[q]].G;
+    EngineItem* it = (EngineItem*)(h + bp.off_items);
+    int64_t n = 0;
+    for (int qi = 0; qi < count; qi++) {
+      const int i = bp.queue[qi];
+      const ProbPlan& p = bp.P[i];
+      for (int u = 0; u < p.S * p.T; u++) it[n++] = EngineItem{ITEM_GRAM, i, u, i, p.G, 0, 0, 0};
+      for (int t = 0; t < p.T; t++) it[n++] = EngineItem{ITEM_REDUCE, i, t, i, p.G, 0, 0, 0};
+      for (int r = 0; r < p.G; r++) it[n++] = EngineItem{ITEM_POWER, i, r, i, p.G, 0, 0, 0};
     }
+    if (n != bp.nitems) return fail(ctx, TSVD_ERR_INTERNAL, "work list size %lld != %d", (long long)n, bp.nitems);
   }
   int* d_status = (int*)(bbase + bp.off_status);
   for (int i = 0; i < count; i++) {
@@ -291,21 +284,16 @@ tsvd_status batch_enqueue(tsvd_ctx* ctx, const tsvd_problem* probs, BatchPlan& b
     if (!rc) rc = finish_grouped_zero_launch(dfj0 + bp.fcount[0], bp.fcount[1], bp.fcols[1], stream);
     if (rc) return from_internal(ctx, rc, "clear outputs");
   }
-  for (auto& g : bp.ggroups) {
-    const int rc = syrk_grouped_launch(g.mode, g.side, (const GramJob*)(bbase + bp.off_gjobs) + g.first, g.count,
-                                       g.units, g.runits, stream);
-    if (rc) return from_internal(ctx, rc, "grouped gram");
-  }
   if (ev && hipEventRecord(ev[1], stream) != hipSuccess) return fail(ctx, TSVD_ERR_HIP, "event");
   size_t lds = 0;
   for (auto& p : bp.P) lds = std::max(lds, p.pp.lds_bytes);
   {
-    const int rc = power_dyn_launch((const PowerArgs*)(bbase + bp.off_pargs), (const int*)(bbase + bp.off_order),
-                                    (const int*)(bbase + bp.off_gsize), count, (int*)(bbase + bp.off_sched), bp.grid,
-                                    lds, (uint64_t*)(bbase + bp.off_zero), bp.zero_words, stream, exit_flags,
-                                    exit_id);
-    if (rc == -2) return fail(ctx, TSVD_ERR_UNSUPPORTED, "batched power kernel does not fit on a CU");
-    if (rc) return from_internal(ctx, rc, "batched power iteration");
+    const int rc = engine_launch((const EngineItem*)(bbase + bp.off_items), bp.nitems,
+                                 (const GramJob*)(bbase + bp.off_gjobs), (const PowerArgs*)(bbase + bp.off_pargs),
+                                 (int*)(bbase + bp.off_ctr), count, bp.grid, lds, (uint64_t*)(bbase + bp.off_zero),
+                                 bp.zero_words, stream, exit_flags, exit_id);
+    if (rc == -2) return fail(ctx, TSVD_ERR_UNSUPPORTED, "batched engine kernel does not fit on a CU");
+    if (rc) return from_internal(ctx, rc, "batched engine");
   }
   if (ev && hipEventRecord(ev[2], stream) != hipSuccess) return fail(ctx, TSVD_ERR_HIP, "event");
   {

@@ -33,15 +33,12 @@ struct GramJob {
   int nt, T, S;
   int64_t kchunk;
   int vec_ok;
-  int pad;
+  int mode;              // MODE_BF16X3 or MODE_FP32
   void* partial;         // S * T * 128 * 128 floats
   void* B;               // d x d (ldb)
   int64_t ldb;
-  int64_t ubegin;        // first workgroup of this job in the partial launch
-  int64_t rbegin;        // first workgroup of this job in the reduce launch
 };
-int syrk_grouped_launch(int mode, int side, const GramJob* d_jobs, int njobs, int64_t units, int64_t runits,
-                        hipStream_t s);
+
 
 // ---- power iteration (power.hip)
 struct PowerArgs {
@@ -77,17 +74,27 @@ struct PowerPlan {
 enum { ERR_NONE = 0, ERR_SPIN = 1, ERR_NONFINITE = 2, ERR_BADSTART = 3 };
 int power_plan(int dtype_bytes, int d, int k, int num_cu, size_t max_lds, int max_blocks_hint, PowerPlan* p);
 int power_launch(int is_f64, const PowerPlan& p, PowerArgs a, hipStream_t stream);
-// batched launch (FP32 Grams), teams formed on the fly: problems order[0..n)
-// (queue order) with team sizes gsize[h]; sched holds 1 + n ints, zero on
-// entry; grid workgroups, one per CU (all resident at once); zero_words of exchange
-// memory at zero_base are cleared first
-// static LDS of the batched power kernel (its dynamic LDS must leave room for it)
-size_t power_dyn_static_lds();
-// exit_flags (optional, grid ints in coherent pinned host memory): each
-// workgroup stores exit_id into its entry when it leaves the launch
-int power_dyn_launch(const PowerArgs* d_probs, const int* d_order, const int* d_gsize, int nprob, int* d_sched,
-                     int grid, size_t lds_bytes, uint64_t* zero_base, size_t zero_words, hipStream_t stream,
-                     int* exit_flags = nullptr, int exit_id = 0);
+// Batched engine (one persistent launch for a whole batch): an ordered list
+// of work items, taken one per fetch in list order.  A problem's items are
+// its Gram units (idx = chunk * T + tile of its GramJob), then its reductions
+// (idx = triangle tile), then the G seats of its power team (idx = rank).
+enum { ITEM_GRAM = 0, ITEM_REDUCE = 1, ITEM_POWER = 2 };
+struct EngineItem {
+  int type, p, idx, job;  // kind, problem, unit / tile / rank, the problem's GramJob
+  int G, pad0, pad1, pad2;
+};
+// static LDS of the engine kernel (its dynamic LDS must leave room for it)
+size_t engine_static_lds();
+// ctr: 4 zeroed ints per problem (Gram units done, reductions done, seats
+// taken) and then the list head; the launch zeroes [zero_base, zero_base +
+// zero_words) first (ctr and the exchange buffers live there); grid
+// workgroups, one per CU, all resident at once.  exit_flags (optional, grid
+// ints in coherent pinned host memory): each workgroup stores exit_id into its
+// entry when it leaves the launch
+int engine_launch(const EngineItem* d_items, int nitems, const GramJob* d_jobs, const PowerArgs* d_probs, int* d_ctr,
+                  int nprob, int grid, size_t lds_bytes, uint64_t* zero_base, size_t zero_words, hipStream_t stream,
+                  int* exit_flags, int exit_id);
+
 
 // ---- finishing pass (finish.hip)
 // one problem of a grouped finishing pass (FP32 A); k = triplets found

@@ -27,11 +27,13 @@
 // HBM) and rounded once to B's storage type.
 #include <math.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "common.h"
 #include "exchange.h"
 #include "internal.h"
+#include "syrk_dev.h"
 
 namespace tsvd {
 
@@ -713,69 +715,102 @@ __global__ __launch_bounds__(256, 1) void power_kernel(PowerArgs a) {
   solve_problem<BT, NV, RR>(a, blockIdx.x, gridDim.x, smem, epoch, nx, np);
 }
 
-// Batch of problems with teams formed on the fly.  The problems sit in a
-// queue (longest first); problem h needs gsize[h] workgroups.  A free
-// workgroup takes the next seat of the queue head (its rank in that team is
-// its seat number) and moves the head on when the problem is full.  Once all
-// seats are taken the team runs the single-problem body with the problem's own
-// exchange buffers and counters starting from zero, then its members go back
-// to the queue.  A problem's arithmetic depends only on its team size and the
-// ranks, never on which workgroups served it, so results are the same in any
-// mix.  sched: [0] queue head, [1 + h] seats taken in problem h (zeroed by the
-// host).  The assembly wait is bounded by join_spin polls.
-__global__ __launch_bounds__(256, 1) void power_dyn_kernel(const PowerArgs* probs, const int* order, const int* gsize,
-                                                           int nprob, int* sched, int64_t join_spin, int* exit_flags,
-                                                           int exit_id) {
+// ---------------------------------------------------------------------------
+// Batched engine: one persistent launch runs a whole batch (every problem's
+// Gram units, their reduction into the problem's B, and its power iteration)
+// from one list of work items that its workgroups take one fetch at a time,
+// in list order.  The list holds, problem after problem in the power queue's
+// order, the problem's Gram units, then its reductions, then the G seats of
+// its team, so the Gram work of later problems runs beside the power teams of
+// earlier ones.  Every wait is on items earlier in the list, which were taken
+// by workgroups that are running and never wait on later items, so the list
+// drains (and every wait is bounded besides).  Completions are published
+// with a device-scope release (the fence writes the unit's stores back past
+// the XCD's L2) and observed with an acquire load, so a reduction reads every
+// partial tile and a team reads all of its B.  The arithmetic of each unit,
+// reduction and team is the stand-alone kernels', so results do not change.
+// ---------------------------------------------------------------------------
+// Poll with relaxed loads (an acquire load per poll would invalidate the
+// XCD's L2 on every poll, under the running teams' feet) and acquire once.
+__device__ __forceinline__ bool wait_count(const int* c, int target, int64_t spin) {
+  int64_t budget = spin;
+  while (__hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    if (--budget <= 0) return false;
+    __builtin_amdgcn_s_sleep(2);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return true;
+}
+
+__device__ __forceinline__ void count_done(int* c) {
+  __hip_atomic_fetch_add(c, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ __launch_bounds__(256, 1) void batch_engine_kernel(const EngineItem* items, int nitems,
+                                                              const GramJob* jobs, const PowerArgs* probs, int* ctr,
+                                                              int nprob, int64_t spin, int* exit_flags, int exit_id) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ int s_h, s_rank;
+  __shared__ int s_t, s_ok;
+  int* head = ctr + 4 * nprob;
   while (true) {
-    if (threadIdx.x == 0) {
-      int h = -1, rank = 0;
-      while (true) {
-        const int cur = __hip_atomic_load(sched, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (cur >= nprob) break;
-        const int seat = atomicAdd(sched + 1 + cur, 1);
-        if (seat < gsize[cur]) { h = cur; rank = seat; break; }
-        atomicCAS(sched, cur, cur + 1);  // full: move the head on (idempotent)
-      }
-      // wait until the team is complete (members may still be finishing an
-      // earlier problem)
-      if (h >= 0) {
-        int64_t budget = join_spin;
-        while (__hip_atomic_load(sched + 1 + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gsize[h]) {
-          if (--budget <= 0) { rank = -1; break; }
-          __builtin_amdgcn_s_sleep(8);
-        }
-      }
-      s_h = h;
-      s_rank = rank;
-    }
+    if (threadIdx.x == 0) s_t = atomicAdd(head, 1);
     __syncthreads();
-    const int h = s_h, rank = s_rank;
-    __syncthreads();
-    if (h < 0) {
-      // tell the host that this workgroup's CU is free again (one vector store
-      // to coherent pinned host memory; the server launches further batches
-      // into CUs released this way)
+    const int t = s_t;
+    if (t >= nitems) {
       if (threadIdx.x == 0 && exit_flags)
         __hip_atomic_store(exit_flags + blockIdx.x, exit_id, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
       return;
     }
-    const PowerArgs a = probs[order[h]];
-    if (rank < 0) {  // the team never assembled: report and leave the problem
-      if (threadIdx.x == 0) atomicMax(a.status + 2, (int)ERR_SPIN);
-      continue;
+    const EngineItem it = items[t];
+    int* pc = ctr + 4 * it.p;
+    const GramJob& j = jobs[it.job];
+    if (it.type == ITEM_GRAM) {
+      const SyrkArgs a = job_args(j);
+      const int s = it.idx / j.T, tt = it.idx % j.T;
+      if (j.mode == MODE_BF16X3) {
+        if (j.side == 0) syrk_unit<MODE_BF16X3, 0>(a, s, tt, smem);
+        else syrk_unit<MODE_BF16X3, 1>(a, s, tt, smem);
+      } else {
+        if (j.side == 0) syrk_unit<MODE_FP32, 0>(a, s, tt, smem);
+        else syrk_unit<MODE_FP32, 1>(a, s, tt, smem);
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) count_done(pc + 0);
+    } else if (it.type == ITEM_REDUCE) {
+      if (threadIdx.x == 0) s_ok = wait_count(pc + 0, j.S * j.T, spin) ? 1 : 0;
+      __syncthreads();
+      if (s_ok) {
+        const int64_t d = j.side == 0 ? j.n : j.m;
+        for (int sub = 0; sub < 16; sub++) {
+          syrk_reduce_unit<float, 128>((const float*)j.partial, j.T, j.S, d, (float*)j.B, j.ldb, 0, it.idx * 16 + sub,
+                                       smem);
+          __syncthreads();
+        }
+      } else if (threadIdx.x == 0) {
+        atomicMax(probs[it.p].status + 2, (int)ERR_SPIN);
+      }
+      if (threadIdx.x == 0) count_done(pc + 1);
+    } else {
+      // a seat of the problem's team: wait for the whole team and for B
+      if (threadIdx.x == 0) {
+        atomicAdd(pc + 2, 1);
+        s_ok = (wait_count(pc + 2, it.G, spin) && wait_count(pc + 1, j.T, spin)) ? 1 : 0;
+      }
+      __syncthreads();
+      const PowerArgs a = probs[it.p];
+      if (!s_ok) {
+        if (threadIdx.x == 0) atomicMax(a.status + 2, (int)ERR_SPIN);
+        __syncthreads();
+        continue;
+      }
+      uint32_t epoch = 0, nx = 0, np = 0;
+      const int d = a.d;
+      if (d <= 1024) solve_problem_call<float, 4, 4>(a, it.idx, it.G, smem, &epoch, &nx, &np);
+      else if (d <= 2048) solve_problem_call<float, 8, 4>(a, it.idx, it.G, smem, &epoch, &nx, &np);
+      else if (d <= 4096) solve_problem_call<float, 16, 2>(a, it.idx, it.G, smem, &epoch, &nx, &np);
+      else if (d <= 8192) solve_problem_call<float, 32, 1>(a, it.idx, it.G, smem, &epoch, &nx, &np);
+      else solve_problem_call<float, 0, 0>(a, it.idx, it.G, smem, &epoch, &nx, &np);
     }
-    uint32_t epoch = 0, nx = 0, np = 0;
-    // the problem's register-row variant (as the single-problem launch picks
-    // it): up to 2-4 rows per wave held in registers when the Gram dimension
-    // allows, the rest of the member's rows in LDS and then HBM
-    const int d = a.d;
-    if (d <= 1024) solve_problem_call<float, 4, 4>(a, rank, gsize[h], smem, &epoch, &nx, &np);
-    else if (d <= 2048) solve_problem_call<float, 8, 4>(a, rank, gsize[h], smem, &epoch, &nx, &np);
-    else if (d <= 4096) solve_problem_call<float, 16, 2>(a, rank, gsize[h], smem, &epoch, &nx, &np);
-    else if (d <= 8192) solve_problem_call<float, 32, 1>(a, rank, gsize[h], smem, &epoch, &nx, &np);
-    else solve_problem_call<float, 0, 0>(a, rank, gsize[h], smem, &epoch, &nx, &np);
     __syncthreads();
   }
 }
@@ -879,33 +914,36 @@ int power_launch(int is_f64, const PowerPlan& p, PowerArgs a, hipStream_t stream
   return 0;
 }
 
-size_t power_dyn_static_lds() {
+size_t engine_static_lds() {
   static size_t bytes = (size_t)-1;
   if (bytes == (size_t)-1) {
     hipFuncAttributes attr;
-    bytes = hipFuncGetAttributes(&attr, (const void*)power_dyn_kernel) == hipSuccess ? attr.sharedSizeBytes : 256;
+    bytes = hipFuncGetAttributes(&attr, (const void*)batch_engine_kernel) == hipSuccess ? attr.sharedSizeBytes : 256;
     (void)hipGetLastError();
   }
   return bytes;
 }
 
-int power_dyn_launch(const PowerArgs* d_probs, const int* d_order, const int* d_gsize, int nprob, int* d_sched,
-                     int grid, size_t lds_bytes, uint64_t* zero_base, size_t zero_words, hipStream_t stream,
-                     int* exit_flags, int exit_id) {
-  if (grid <= 0 || nprob <= 0) return 0;
+int engine_launch(const EngineItem* d_items, int nitems, const GramJob* d_jobs, const PowerArgs* d_probs, int* d_ctr,
+                  int nprob, int grid, size_t lds_bytes, uint64_t* zero_base, size_t zero_words, hipStream_t stream,
+                  int* exit_flags, int exit_id) {
+  if (grid <= 0 || nitems <= 0) return 0;
   if (zero_words) {
     hipLaunchKernelGGL(zero_words_kernel, dim3(256), dim3(256), 0, stream, zero_base, zero_words);
     TSVD_HIP_TRY(hipGetLastError());
   }
-  const void* fn = (const void*)power_dyn_kernel;
+  // a Gram unit's LDS (both stages of both panels) must fit as well
+  lds_bytes = std::max(lds_bytes, std::max(SyrkCfg<MODE_BF16X3>::LDS, SyrkCfg<MODE_FP32>::LDS));
+  const void* fn = (const void*)batch_engine_kernel;
   TSVD_HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
   int per_cu = 0;
   TSVD_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, lds_bytes));
   if (per_cu < 1) return -2;
-  int64_t join_spin = (int64_t)1 << 30;
-  void* args[] = {(void*)&d_probs, (void*)&d_order,   (void*)&d_gsize,    (void*)&nprob,
-                  (void*)&d_sched, (void*)&join_spin, (void*)&exit_flags, (void*)&exit_id};
+  // all workgroups resident at once (teams wait for their members)
   if ((int64_t)grid > (int64_t)per_cu * max_cus()) return -2;
+  int64_t spin = (int64_t)1 << 26;
+  void* args[] = {(void*)&d_items, (void*)&nitems, (void*)&d_jobs, (void*)&d_probs, (void*)&d_ctr,
+                  (void*)&nprob,   (void*)&spin,   (void*)&exit_flags, (void*)&exit_id};
   TSVD_HIP_TRY(hipLaunchKernel(fn, dim3(grid), dim3(256), args, lds_bytes, stream));
   return 0;
 }

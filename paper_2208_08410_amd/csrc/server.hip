@@ -7,11 +7,11 @@
 //      copied on the copy stream at once;
 //   2. launches admitted requests as one batch (grouped Gram, team power
 //      kernel, grouped finish) on an idle lane -- each lane is a compute
-//      stream -- into the CUs that no running power launch holds;
+//      stream -- into the CUs that no running engine launch holds;
 //   3. when a lane's completion event has fired, releases that batch's memory
 //      and completes its tickets (latency = completion - submission, host
 //      clock).
-// The persistent power launch of a batch holds one CU per workgroup until
+// The persistent engine launch of a batch holds one CU per workgroup until
 // that workgroup finds the batch's queue empty; each workgroup then stores
 // the batch's id into its entry of a flag array in coherent pinned host
 // memory before it exits.  The worker counts a running launch's CUs as its
@@ -140,9 +140,9 @@ struct Lane {
   char* hpin = nullptr;  // pinned host staging of the batch's descriptors and results
   size_t hpin_bytes = 0;
   int* flags = nullptr;  // coherent pinned host memory, one int per power workgroup
-  int batch_id = 0;      // what the current power launch's workgroups store on exit
+  int batch_id = 0;      // what the current engine launch's workgroups store on exit
   int grid = 0;          // its workgroups
-  // CUs the lane's power launch may still hold: its grid less the workgroups that have left
+  // CUs the lane's engine launch may still hold: its grid less the workgroups that have left
   int live() const {
     if (!active) return 0;
     int gone = 0;
@@ -280,7 +280,7 @@ void launch(tsvd_server* s) {
       break;
     }
   if (!L) return;
-  // CUs no running power launch holds.  Beside a running batch, a new one
+  // CUs no running engine launch holds.  Beside a running batch, a new one
   // launches only once 7/8 of the chip is free (a batch's grid is fixed at
   // launch: started into a small remainder, its teams would queue on few CUs
   // long after the running batch has ended; at the serving mix, two lanes gave
