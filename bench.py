@@ -84,6 +84,9 @@ def parse():
     ap.add_argument("--max-batch", type=int, default=0, help="serve: requests per batch launch at most (0 = all)")
     ap.add_argument("--lanes", type=int, default=0, help="serve: batches on the device at once (0 = library)")
     ap.add_argument("--batch-size", type=int, default=64, help="batch: problems per tsvd_dense_batched call")
+    ap.add_argument("--gram-units", default="library", choices=["library", "tuned", "64", "128"],
+                    help="batch: batched Gram unit shapes per Gram-dimension class (library choice, the "
+                         "autotuner's per-class choice measured first, or one tile edge for every class)")
     ap.add_argument("--pool-gen", default="gpu", choices=["gpu", "cpu"],
                     help="serve/batch: build the matrices on the GPU or on the host (then copy)")
     return ap.parse_args()
@@ -316,8 +319,20 @@ def batch_main(a):
     pick = synth.rng(a.seed, 89).integers(0, a.pool, size=a.batch_size)
     probs = [dict(A=pool[j][0], k=int(k), eps=a.eps, v0=pool[j][1][:int(k)], gram="bf16x3") for j, k in zip(pick, kch)]
     ctx = P.Context(0)
-    if a.team_kib:
-        P.set_tuning(ctx, team_kib=a.team_kib)
+    tune = {"team_kib": a.team_kib}
+    units = None
+    if a.gram_units == "tuned":
+        import tempfile
+
+        from paper_2208_08410_amd import autotune as T
+        progress("tuning the batched Gram unit shape per Gram-dimension class")
+        with tempfile.TemporaryDirectory() as td:
+            tuner = T.Tuner(ctx, os.path.join(td, "tuning.json"), reps=2)
+            units = {int(c): list(v) for c, v in tuner.tune_gram_classes([tuple(p["A"].shape) for p in probs]).items()}
+            tune.update(tuner.class_tuning())
+    elif a.gram_units in ("64", "128"):
+        tune["group_tile"] = [int(a.gram_units)] * P.GRAM_CLASSES
+    P.set_tuning(ctx, **tune)
     progress(f"batch of {a.batch_size}: {a.warmup} warm-up and {a.steps} timed calls")
     for _ in range(a.warmup):
         P.tsvd_dense_batched(ctx, probs)
@@ -351,7 +366,8 @@ def batch_main(a):
         "config": {"workload": f"batch of {a.batch_size} problems from the serving mix (m log-uniform [1024, 65536], "
                                f"n [128, 4096], k in {{8,16,32,64}}, s_i = 0.95^i), one tsvd_dense_batched call per "
                                f"step, eps={a.eps}", "batch_size": a.batch_size, "pool": a.pool,
-                   "team_kib": a.team_kib},
+                   "team_kib": a.team_kib, "gram_units": a.gram_units},
+        "gram_units_tuned": units,
         "triplets_per_s": float(sum(int(k) for k in kch)) * a.steps / dt,
         "phase_ms": {"gram": info0["t_gram_ms"], "power": info0["t_eig_ms"], "finish": info0["t_final_ms"]},
         "statuses": statuses,

@@ -148,6 +148,9 @@ const char* tsvd_status_string(tsvd_status s);
 /* Message of the last failing call on `ctx` ("" if none).  Owned by ctx. */
 const char* tsvd_last_error(const tsvd_ctx* ctx);
 
+/* Gram-dimension classes of the batched Gram's per-class unit shapes (tsvd_tuning). */
+#define TSVD_GRAM_CLASSES 8
+
 /* Launch-shape tuning of a context (chosen by the library when 0).  The
  * autotuner (paper_2208_08410_amd.autotune) measures candidates per shape class
  * and sets these before a call. */
@@ -168,6 +171,15 @@ typedef struct {
   int32_t power_path;    /* Gram power iteration: 0 = the on-chip persistent kernel when the iterate fits
                             it, else the host-driven loop of HBM-streamed B x products; 1 = always that
                             loop (B is then left undeflated: deflation is a projection per iteration) */
+  /* Batched Gram work-unit shape per Gram-dimension class c (TSVD_GRAM_CLASSES classes: c = 0 for
+     d <= 128, c for 2^(6+c) < d <= 2^(7+c), the last for d > 8192).  A unit is one tile_edge x
+     tile_edge triangle tile over a chunk of contraction rows.  The edge does not change any result
+     bit (every Gram entry sums the same contraction steps in the same order); the chunk length sets
+     the split-K order of the FP32 sums, per problem, so a problem still gives the same bits alone and
+     in any mix. */
+  int32_t group_tile[TSVD_GRAM_CLASSES];       /* tile edge of class c: 0 = library choice, 64 or 128 */
+  int32_t group_kchunk_cls[TSVD_GRAM_CLASSES]; /* contraction rows per unit of class c: 0 = group_kchunk;
+                                                  range [32, 2^20] */
 } tsvd_tuning;
 
 /* Set / read the context's tuning.  INVALID_ARG for out-of-range values. */

@@ -30,6 +30,8 @@ __all__ = [
     "Server",
     "set_tuning",
     "get_tuning",
+    "gram_class",
+    "GRAM_CLASSES",
     "Csr",
     "tsvd_csr_create",
     "tsvd_csr_create_pinned",
@@ -86,6 +88,18 @@ class TsvdOpts(ctypes.Structure):
     ]
 
 
+GRAM_CLASSES = 8  # Gram-dimension classes of the batched Gram's unit shapes
+
+
+def gram_class(d: int) -> int:
+    """Class of a Gram dimension: 0 for d <= 128, c for 2^(6+c) < d <= 2^(7+c),
+    the last class for anything larger."""
+    c = 0
+    while c < GRAM_CLASSES - 1 and d > (128 << c):
+        c += 1
+    return c
+
+
 class TsvdTuning(ctypes.Structure):
     _fields_ = [
         ("gram_tile", ctypes.c_int32),
@@ -96,6 +110,8 @@ class TsvdTuning(ctypes.Structure):
         ("sparse_row_bits", ctypes.c_int32),
         ("sparse_col_bits", ctypes.c_int32),
         ("power_path", ctypes.c_int32),
+        ("group_tile", ctypes.c_int32 * GRAM_CLASSES),
+        ("group_kchunk_cls", ctypes.c_int32 * GRAM_CLASSES),
     ]
 
 
@@ -294,20 +310,37 @@ TUNING_FIELDS = ("gram_tile", "gram_chunks", "power_blocks", "team_kib", "group_
 
 
 def set_tuning(ctx: Context, gram_tile: int = 0, gram_chunks: int = 0, power_blocks: int = 0, team_kib: int = 0,
-               group_kchunk: int = 0, sparse_row_bits: int = 0, sparse_col_bits: int = 0, power_path: int = 0):
-    """Set the context's launch-shape tuning (0 = library choice)."""
+               group_kchunk: int = 0, sparse_row_bits: int = 0, sparse_col_bits: int = 0, power_path: int = 0,
+               group_tile=None, group_kchunk_cls=None):
+    """Set the context's launch-shape tuning (0 = library choice).
+    group_tile / group_kchunk_cls: the batched Gram's unit shape per
+    Gram-dimension class (gram_class), as a sequence of GRAM_CLASSES entries
+    or a {class: value} dict; missing classes are 0."""
     t = TsvdTuning()
     t.gram_tile, t.gram_chunks, t.power_blocks = int(gram_tile), int(gram_chunks), int(power_blocks)
     t.team_kib, t.group_kchunk = int(team_kib), int(group_kchunk)
     t.sparse_row_bits, t.sparse_col_bits = int(sparse_row_bits), int(sparse_col_bits)
     t.power_path = int(power_path)
+    for name, val in (("group_tile", group_tile), ("group_kchunk_cls", group_kchunk_cls)):
+        arr = getattr(t, name)
+        if val is None:
+            continue
+        items = val.items() if isinstance(val, dict) else enumerate(val)
+        for c, v in items:
+            c = int(c)
+            if not 0 <= c < GRAM_CLASSES:
+                raise ValueError(f"{name}: class {c} outside [0, {GRAM_CLASSES})")
+            arr[c] = int(v)
     ctx.check(ctx.lib.tsvd_ctx_set_tuning(ctx.handle, ctypes.byref(t)))
 
 
 def get_tuning(ctx: Context) -> dict:
     t = TsvdTuning()
     ctx.check(ctx.lib.tsvd_ctx_get_tuning(ctx.handle, ctypes.byref(t)))
-    return {f: getattr(t, f) for f in TUNING_FIELDS}
+    out = {f: getattr(t, f) for f in TUNING_FIELDS}
+    out["group_tile"] = list(t.group_tile)
+    out["group_kchunk_cls"] = list(t.group_kchunk_cls)
+    return out
 
 
 def _stream(stream):

@@ -3,8 +3,9 @@
 The library's kernels take their launch shapes from the context's tuning
 (tsvd_ctx_set_tuning): the BF16X3 Gram tile edge, the split-K chunk count, the
 power launch's workgroup count, and, for batches, the team size rule and the
-grouped Gram's chunk length.  None of these changes what is computed (the
-Gram's chunk order changes FP32 rounding only); they change speed.
+batched Gram's work-unit shape (tile edge and chunk length) per Gram-dimension
+class.  None of these changes what is computed (the Gram's chunk order changes
+FP32 rounding only); they change speed.
 
 The tuner measures candidates per *shape class* through the public entry
 points, with HIP events on the caller's stream, keeps the fastest, and stores
@@ -14,6 +15,8 @@ the choice in a JSON cache so later processes reuse it:
     tuner.tune_dense(A, gram="bf16x3", k=8)     # measures, stores
     tuner.apply_dense(m, n, "bf16x3")           # sets the stored tuning
     tuner.tune_batch(problems)                  # team_kib / group_kchunk
+    tuner.tune_gram_classes(shapes)             # batched Gram unit per class
+    tuner.apply_batch(shapes)                   # both, for a batch
 
 A shape class buckets the Gram dimension d and the contraction length K to
 powers of two (and the Gram mode and side), so that one measurement serves
@@ -27,7 +30,7 @@ import math
 import os
 import time
 
-from . import Context, get_tuning, set_tuning
+from . import GRAM_CLASSES, Context, gram_class, get_tuning, set_tuning
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "paper_2208_08410_amd", "tuning.json")
 
@@ -78,6 +81,19 @@ def batch_candidates():
     return [(tk, kc) for tk in (64, 128, 256, 512, 1024) for kc in (1024, 2048, 4096)]
 
 
+def gram_unit_key(cls: int) -> str:
+    """Cache key of a Gram-dimension class's batched unit shape."""
+    return f"gram_unit/c{int(cls)}"
+
+
+def gram_unit_candidates(K_max: int):
+    """(tile edge, chunk rows) pairs of the batched Gram's work unit for a
+    class whose longest contraction is K_max: chunk lengths past 2 K_max all
+    give one chunk and are left out."""
+    kcs = [kc for kc in (512, 1024, 2048, 4096, 8192) if kc <= max(512, 2 * int(K_max))]
+    return [(t, kc) for t in (64, 128) for kc in kcs]
+
+
 class Tuner:
     def __init__(self, ctx: Context, cache_path: str | None = None, reps: int = 3):
         self.ctx = ctx
@@ -102,16 +118,37 @@ class Tuner:
 
     def apply(self, key: str) -> bool:
         """Set the stored tuning of `key` on the context (library defaults if
-        the class was never tuned).  Returns whether an entry was found."""
+        the class was never tuned), with every class's stored batched-Gram
+        unit shape.  Returns whether an entry was found."""
         t = self.lookup(key)
-        set_tuning(self.ctx, **(t or {}))
+        merged = dict(t or {})
+        merged.update(self.class_tuning())
+        set_tuning(self.ctx, **merged)
         return t is not None
 
     def apply_dense(self, m: int, n: int, gram: str, branch: int = 0) -> bool:
         return self.apply(dense_class(m, n, gram, branch))
 
+    def class_tuning(self) -> dict:
+        """The stored batched-Gram unit shapes of every class, as the
+        group_tile / group_kchunk_cls arguments of set_tuning (0 = library
+        choice for classes never tuned)."""
+        tiles, kcs = [0] * GRAM_CLASSES, [0] * GRAM_CLASSES
+        for c in range(GRAM_CLASSES):
+            e = self.lookup(gram_unit_key(c))
+            if e:
+                tiles[c], kcs[c] = int(e["group_tile"]), int(e["group_kchunk"])
+        return {"group_tile": tiles, "group_kchunk_cls": kcs}
+
     def apply_batch(self, shapes) -> bool:
-        return self.apply(batch_class(shapes))
+        """Set the batch class's stored team rule and chunk length together
+        with every class's stored Gram unit shape.  Returns whether the batch
+        class had an entry."""
+        t = self.lookup(batch_class(shapes))
+        merged = dict(t or {})
+        merged.update(self.class_tuning())
+        set_tuning(self.ctx, **merged)
+        return t is not None
 
     # ---- measurement
     def _time(self, fn) -> float:
@@ -198,3 +235,46 @@ class Tuner:
         if save:
             self.save()
         return tuning
+
+    def tune_gram_classes(self, shapes, per_class: int = 16, seed: int = 7, save: bool = True) -> dict:
+        """Tune the batched Gram's work unit (tile edge, chunk rows) per
+        Gram-dimension class.  For every class that `shapes` (a list of (m, n))
+        reaches, a batch of up to `per_class` of its shapes, with random A,
+        one triplet and one fixed iteration (so that the Gram dominates the
+        call), is timed under each candidate; the other classes keep their
+        current entries.  Returns {class: (tile, chunk rows)}."""
+        import torch
+        from . import tsvd_dense_batched
+        by_cls = {}
+        for m, n in shapes:
+            by_cls.setdefault(gram_class(min(m, n)), []).append((int(m), int(n)))
+        saved = get_tuning(self.ctx)
+        gen = torch.Generator(device="cpu").manual_seed(int(seed))
+        dev = torch.device("cuda", self.ctx.device)
+        chosen = {}
+        for c in sorted(by_cls):
+            sub = by_cls[c][:per_class]
+            probs = []
+            for m, n in sub:
+                A = torch.randn((m, n), generator=gen, dtype=torch.float32).to(dev)
+                v0 = torch.randn((1, min(m, n)), generator=gen, dtype=torch.float64).to(dev)
+                probs.append({"A": A, "k": 1, "eps": 0.0, "v0": v0, "fixed_iters": [1], "gram": "bf16x3"})
+            K_max = max(max(m, n) for m, n in sub)
+            trials = []
+            best, best_ms = None, float("inf")
+            for tile, kc in gram_unit_candidates(K_max):
+                cur = self.class_tuning()
+                cur["group_tile"][c], cur["group_kchunk_cls"][c] = tile, kc
+                base = dict(saved)
+                base.update(cur)
+                set_tuning(self.ctx, **base)
+                ms = self._time(lambda: tsvd_dense_batched(self.ctx, probs, raise_errors=True))
+                trials.append({"group_tile": tile, "group_kchunk": kc, "ms": ms})
+                if ms < best_ms:
+                    best, best_ms = (tile, kc), ms
+            self._record(gram_unit_key(c), {"group_tile": best[0], "group_kchunk": best[1]}, best_ms, trials)
+            chosen[c] = best
+        set_tuning(self.ctx, **saved)
+        if save:
+            self.save()
+        return chosen

@@ -133,6 +133,12 @@ tsvd_status tsvd_ctx_set_tuning(tsvd_ctx* ctx, const tsvd_tuning* t) {
   if (t->group_kchunk != 0 && (t->group_kchunk < 32 || t->group_kchunk > (1 << 20)))
     return fail(ctx, TSVD_ERR_INVALID_ARG, "group_kchunk must be 0 or in [32, 2^20]");
   if (t->power_path != 0 && t->power_path != 1) return fail(ctx, TSVD_ERR_INVALID_ARG, "power_path must be 0 or 1");
+  for (int c = 0; c < TSVD_GRAM_CLASSES; c++) {
+    if (t->group_tile[c] != 0 && t->group_tile[c] != 64 && t->group_tile[c] != 128)
+      return fail(ctx, TSVD_ERR_INVALID_ARG, "group_tile[%d] must be 0, 64 or 128", c);
+    if (t->group_kchunk_cls[c] != 0 && (t->group_kchunk_cls[c] < 32 || t->group_kchunk_cls[c] > (1 << 20)))
+      return fail(ctx, TSVD_ERR_INVALID_ARG, "group_kchunk_cls[%d] must be 0 or in [32, 2^20]", c);
+  }
   ctx->tuning = *t;
   return TSVD_OK;
 }

@@ -15,6 +15,7 @@ struct ProbPlan {
   int64_t d = 0, K = 0;
   int k = 0;
   int64_t ldb = 0;
+  int bm = 0;                 // Gram tile edge (64 or 128)
   int nt = 0, T = 0, S = 0;   // Gram tiles per side, triangle tiles, split-K chunks
   int64_t kchunk = 0;
   int G = 0;                  // power team size (workgroups)

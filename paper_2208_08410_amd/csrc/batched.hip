@@ -5,7 +5,8 @@
 // of Algorithm 2/3): only the scheduling differs.
 //   Engine: one persistent launch whose workgroups take work items from one
 //           list in order: per problem (queued longest first) its Gram units
-//           (split-K chunk x 128x128 triangle tile), the reduction of each
+//           (split-K chunk x triangle tile, the unit shape per Gram-dimension
+//           class from the context's tuning), the reduction of each
 //           tile's chunk partials into B, and the seats of its power team; a
 //           team runs the single-problem body (a team is to one problem what
 //           the whole grid is to a single call).  Later problems' Gram units
@@ -31,7 +32,17 @@ namespace tsvd {
 
 namespace {
 
-constexpr int kTile = 128;  // grouped Gram tile edge
+// Gram-dimension class of the per-class unit shapes: 0 for d <= 128, c for
+// 2^(6+c) < d <= 2^(7+c), the last class for anything larger
+int gram_class(int64_t d) {
+  int c = 0;
+  while (c < TSVD_GRAM_CLASSES - 1 && d > ((int64_t)128 << c)) c++;
+  return c;
+}
+
+// library choice of the tile edge per class: 64 below d = 256, where a
+// 128 edge would compute up to twice the triangle's area
+int default_tile(int cls) { return cls == 0 ? 64 : 128; }
 
 // workgroups a problem's power iteration runs on: enough to hold its Gram at
 // team_kib per CU, at least 4 rows per workgroup
@@ -54,7 +65,7 @@ tsvd_status batch_plan(tsvd_ctx* ctx, int count, const tsvd_problem* probs, Batc
   // default: 256 KiB of the problem's Gram per member, about what a member
   // holds on chip (LDS rows plus register rows) up to a dimension of 8192
   const int team_kib = ctx->tuning.team_kib > 0 ? ctx->tuning.team_kib : 256;
-  const int64_t kc_target = ctx->tuning.group_kchunk > 0 ? ctx->tuning.group_kchunk : 2048;
+  const int64_t kc_default = ctx->tuning.group_kchunk > 0 ? ctx->tuning.group_kchunk : 2048;
   bp.count = count;
   bp.P.assign(count, ProbPlan());
   for (int i = 0; i < count; i++) {
@@ -86,9 +97,12 @@ tsvd_status batch_plan(tsvd_ctx* ctx, int count, const tsvd_problem* probs, Batc
     if (p.d > 32768)
       return fail(ctx, TSVD_ERR_UNSUPPORTED, "problem %d: Gram dimension %lld too large for the batched path", i,
                   (long long)p.d);
-    // Gram split-K: chunks of about kc_target contraction rows, at most 4096
-    // partial tiles per problem
-    p.nt = (int)((p.d + kTile - 1) / kTile);
+    // Gram work units: the class's tile edge, split-K chunks of about the
+    // class's contraction rows, at most 4096 partial tiles per problem
+    const int cls = gram_class(p.d);
+    p.bm = ctx->tuning.group_tile[cls] > 0 ? ctx->tuning.group_tile[cls] : default_tile(cls);
+    const int64_t kc_target = ctx->tuning.group_kchunk_cls[cls] > 0 ? ctx->tuning.group_kchunk_cls[cls] : kc_default;
+    p.nt = (int)((p.d + p.bm - 1) / p.bm);
     p.T = p.nt * (p.nt + 1) / 2;
     int64_t S = std::max<int64_t>(1, (p.K + kc_target / 2) / kc_target);
     S = std::min<int64_t>(S, std::max<int64_t>(1, 4096 / p.T));
@@ -108,7 +122,7 @@ tsvd_status batch_plan(tsvd_ctx* ctx, int count, const tsvd_problem* probs, Batc
     size_t off = 0;
     auto take = [&](size_t b) { off = align256(off); const size_t o2 = off; off += b; return o2; };
     p.off_B = take((size_t)p.d * p.ldb * 4);
-    p.off_partial = take((size_t)p.S * p.T * kTile * kTile * 4);
+    p.off_partial = take((size_t)p.S * p.T * p.bm * p.bm * 4);
     p.off_ssq = take((size_t)(p.nb + 2) * p.k * 8);
     p.ws_bytes = align256(off);
   }
@@ -190,7 +204,7 @@ tsvd_status batch_enqueue(tsvd_ctx* ctx, const tsvd_problem* probs, BatchPlan& b
     const tsvd_problem& q = probs[i];
     GramJob& j = gj[i];
     j.A = q.A; j.m = q.m; j.n = q.n; j.lda = q.lda; j.side = p.side; j.mode = p.mode;
-    j.nt = p.nt; j.T = p.T; j.S = p.S; j.kchunk = p.kchunk;
+    j.nt = p.nt; j.T = p.T; j.S = p.S; j.kchunk = p.kchunk; j.bm = p.bm;
     j.vec_ok = (((uintptr_t)q.A & 15) == 0) && (q.lda % 4 == 0);
     j.partial = pbase[i] + p.off_partial;
     j.B = pbase[i] + p.off_B;

@@ -25,7 +25,7 @@ int syrk_plan(int mode, int64_t d, int64_t K, int64_t rows_per_block, int num_cu
 int syrk_launch(int mode, int side, const void* A, int64_t m, int64_t n, int64_t lda, const SyrkPlan& p,
                 void* partial, void* B, int64_t ldb, int accumulate, hipStream_t stream);
 
-// one problem of a grouped (batched) Gram launch; 128-wide tiles
+// one problem's Gram in the batched engine
 struct GramJob {
   const void* A;
   int64_t m, n, lda;
@@ -34,7 +34,8 @@ struct GramJob {
   int64_t kchunk;
   int vec_ok;
   int mode;              // MODE_BF16X3 or MODE_FP32
-  void* partial;         // S * T * 128 * 128 floats
+  int bm, pad;           // triangle tile edge: 64 or 128
+  void* partial;         // S * T * bm * bm floats
   void* B;               // d x d (ldb)
   int64_t ldb;
 };

@@ -746,6 +746,30 @@ __device__ __forceinline__ void count_done(int* c) {
   __hip_atomic_fetch_add(c, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// one Gram work unit of a batched problem (tile edge BM)
+template <int BM>
+__device__ __forceinline__ void engine_gram_unit(const GramJob& j, const SyrkArgs& a, int s, int t,
+                                                 unsigned char* smem) {
+  if (j.mode == MODE_BF16X3) {
+    if (j.side == 0) syrk_unit<MODE_BF16X3, 0, BM>(a, s, t, smem);
+    else syrk_unit<MODE_BF16X3, 1, BM>(a, s, t, smem);
+  } else {
+    if (j.side == 0) syrk_unit<MODE_FP32, 0, BM>(a, s, t, smem);
+    else syrk_unit<MODE_FP32, 1, BM>(a, s, t, smem);
+  }
+}
+
+// reduction of one triangle tile's chunk partials into B, 32 x 32 at a time
+template <int BM>
+__device__ __forceinline__ void engine_reduce_tile(const GramJob& j, int tile, unsigned char* smem) {
+  constexpr int SUBS = (BM / 32) * (BM / 32);
+  const int64_t d = j.side == 0 ? j.n : j.m;
+  for (int sub = 0; sub < SUBS; sub++) {
+    syrk_reduce_unit<float, BM>((const float*)j.partial, j.T, j.S, d, (float*)j.B, j.ldb, 0, tile * SUBS + sub, smem);
+    __syncthreads();
+  }
+}
+
 __global__ __launch_bounds__(256, 1) void batch_engine_kernel(const EngineItem* items, int nitems,
                                                               const GramJob* jobs, const PowerArgs* probs, int* ctr,
                                                               int nprob, int64_t spin, int* exit_flags, int exit_id) {
@@ -767,25 +791,16 @@ __global__ __launch_bounds__(256, 1) void batch_engine_kernel(const EngineItem* 
     if (it.type == ITEM_GRAM) {
       const SyrkArgs a = job_args(j);
       const int s = it.idx / j.T, tt = it.idx % j.T;
-      if (j.mode == MODE_BF16X3) {
-        if (j.side == 0) syrk_unit<MODE_BF16X3, 0>(a, s, tt, smem);
-        else syrk_unit<MODE_BF16X3, 1>(a, s, tt, smem);
-      } else {
-        if (j.side == 0) syrk_unit<MODE_FP32, 0>(a, s, tt, smem);
-        else syrk_unit<MODE_FP32, 1>(a, s, tt, smem);
-      }
+      if (j.bm == 64) engine_gram_unit<64>(j, a, s, tt, smem);
+      else engine_gram_unit<128>(j, a, s, tt, smem);
       __syncthreads();
       if (threadIdx.x == 0) count_done(pc + 0);
     } else if (it.type == ITEM_REDUCE) {
       if (threadIdx.x == 0) s_ok = wait_count(pc + 0, j.S * j.T, spin) ? 1 : 0;
       __syncthreads();
       if (s_ok) {
-        const int64_t d = j.side == 0 ? j.n : j.m;
-        for (int sub = 0; sub < 16; sub++) {
-          syrk_reduce_unit<float, 128>((const float*)j.partial, j.T, j.S, d, (float*)j.B, j.ldb, 0, it.idx * 16 + sub,
-                                       smem);
-          __syncthreads();
-        }
+        if (j.bm == 64) engine_reduce_tile<64>(j, it.idx, smem);
+        else engine_reduce_tile<128>(j, it.idx, smem);
       } else if (threadIdx.x == 0) {
         atomicMax(probs[it.p].status + 2, (int)ERR_SPIN);
       }

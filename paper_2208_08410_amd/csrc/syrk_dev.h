@@ -10,18 +10,25 @@
 
 namespace tsvd {
 
-template <int MODE> struct SyrkCfg;
-template <> struct SyrkCfg<MODE_BF16X3> {
-  static constexpr int BM = 128, BK = 32, LDK = BK + 8;  // LDS row of bf16
+// BM: triangle tile edge.  BF16X3 and FP32 take 128 (the stand-alone 128-tile
+// launch and the batched engine) or 64 (the engine, for small Gram
+// dimensions); a tile's partial sums do not depend on its edge, because every
+// element is accumulated over the same contraction steps in the same order.
+template <int MODE, int BM_ = (MODE == MODE_FP64 ? 64 : 128)> struct SyrkCfg;
+template <int BM_> struct SyrkCfg<MODE_BF16X3, BM_> {
+  static_assert(BM_ == 64 || BM_ == 128, "BF16X3 tile edge");
+  static constexpr int BM = BM_, BK = 32, LDK = BK + 8;  // LDS row of bf16
   using AT = float; using OT = float;
   static constexpr size_t LDS = (size_t)2 * 2 * 2 * BM * LDK * 2;  // stages x panels x hi/lo
 };
-template <> struct SyrkCfg<MODE_FP32> {
-  static constexpr int BM = 128, BK = 32, LDK = BK + 4;  // LDS row of float
+template <int BM_> struct SyrkCfg<MODE_FP32, BM_> {
+  static_assert(BM_ == 64 || BM_ == 128, "FP32 tile edge");
+  static constexpr int BM = BM_, BK = 32, LDK = BK + 4;  // LDS row of float
   using AT = float; using OT = float;
   static constexpr size_t LDS = (size_t)2 * 2 * BM * LDK * 4;      // stages x panels
 };
-template <> struct SyrkCfg<MODE_FP64> {
+template <int BM_> struct SyrkCfg<MODE_FP64, BM_> {
+  static_assert(BM_ == 64, "FP64 tile edge");
   static constexpr int BM = 64, BK = 16, LDK = BK + 2;   // LDS row of double
   using AT = double; using OT = double;
   static constexpr size_t LDS = (size_t)2 * 2 * BM * LDK * 8;
@@ -74,34 +81,43 @@ __device__ __forceinline__ void split_bf16(float a, __bf16& hi, __bf16& lo) {
 
 // ---------------------------------------------------------------------------
 // BF16X3 staging: 4 consecutive k for one LDS column per 8-byte LDS store.
+// A thread holds 4 k x CW columns (SIDE 0) or BM/32 panel rows x 4 k (SIDE 1)
+// in v; with BM = 64 only the first half of v's inner (SIDE 0) or outer
+// (SIDE 1) index is used.
 // ---------------------------------------------------------------------------
-template <int SIDE>
+template <int SIDE, int BM = 128>
 __device__ __forceinline__ void load_panel_bf16(const SyrkArgs& a, int64_t c0, int64_t k0, int64_t kend,
                                                 float (&v)[4][4]) {
   const float* A = (const float*)a.A;
   const int tid = threadIdx.x;
   if (SIDE == 0) {
-    // rows k (contraction) x columns c of A; thread covers 4 rows x 4 columns
+    // rows k (contraction) x columns c of A; thread covers 4 rows x CW columns
+    constexpr int CW = BM / 32;
     const int rg = tid & 7, cg = tid >> 3;
-    const int64_t c = c0 + 4 * cg;
+    const int64_t c = c0 + CW * cg;
 #pragma unroll
     for (int j = 0; j < 4; j++) {
       const int64_t k = k0 + 4 * rg + j;
       const float* p = A + k * a.lda + c;
-      if (k < kend && a.vec_ok && c + 3 < a.d) {
-        float4 f = *(const float4*)p;
-        v[j][0] = f.x; v[j][1] = f.y; v[j][2] = f.z; v[j][3] = f.w;
+      if (k < kend && a.vec_ok && c + CW - 1 < a.d) {
+        if constexpr (CW == 4) {
+          float4 f = *(const float4*)p;
+          v[j][0] = f.x; v[j][1] = f.y; v[j][2] = f.z; v[j][3] = f.w;
+        } else {
+          float2 f = *(const float2*)p;
+          v[j][0] = f.x; v[j][1] = f.y;
+        }
       } else {
 #pragma unroll
-        for (int i = 0; i < 4; i++) v[j][i] = (k < kend && c + i < a.d) ? p[i] : 0.0f;
+        for (int i = 0; i < CW; i++) v[j][i] = (k < kend && c + i < a.d) ? p[i] : 0.0f;
       }
     }
   } else {
-    // rows c of A (panel rows) x columns k (contraction); thread covers 4 rows x 4 k
+    // rows c of A (panel rows) x columns k (contraction); thread covers BM/32 rows x 4 k
     const int kg = tid & 7, rr = tid >> 3;
     const int64_t k = k0 + 4 * kg;
 #pragma unroll
-    for (int q = 0; q < 4; q++) {
+    for (int q = 0; q < BM / 32; q++) {
       const int64_t c = c0 + rr + 32 * q;
       const float* p = A + c * a.lda + k;
       if (c < a.d && a.vec_ok && k + 3 < kend) {
@@ -115,25 +131,26 @@ __device__ __forceinline__ void load_panel_bf16(const SyrkArgs& a, int64_t c0, i
   }
 }
 
-template <int SIDE>
+template <int SIDE, int BM = 128>
 __device__ __forceinline__ void store_panel_bf16(__bf16* hi, __bf16* lo, const float (&v)[4][4]) {
-  constexpr int LDK = SyrkCfg<MODE_BF16X3>::LDK;
+  constexpr int LDK = SyrkCfg<MODE_BF16X3, BM>::LDK;
   const int tid = threadIdx.x;
   if (SIDE == 0) {
+    constexpr int CW = BM / 32;
     const int rg = tid & 7, cg = tid >> 3;
 #pragma unroll
-    for (int i = 0; i < 4; i++) {          // column 4cg+i holds k = 4rg..4rg+3 = v[0..3][i]
+    for (int i = 0; i < CW; i++) {         // column CW*cg+i holds k = 4rg..4rg+3 = v[0..3][i]
       bf16x4 h, l;
 #pragma unroll
       for (int j = 0; j < 4; j++) { __bf16 x, y; split_bf16(v[j][i], x, y); h[j] = x; l[j] = y; }
-      const int off = (4 * cg + i) * LDK + 4 * rg;
+      const int off = (CW * cg + i) * LDK + 4 * rg;
       *(bf16x4*)(hi + off) = h;
       *(bf16x4*)(lo + off) = l;
     }
   } else {
     const int kg = tid & 7, rr = tid >> 3;
 #pragma unroll
-    for (int q = 0; q < 4; q++) {          // panel row rr+32q holds k = 4kg..4kg+3 = v[q][0..3]
+    for (int q = 0; q < BM / 32; q++) {    // panel row rr+32q holds k = 4kg..4kg+3 = v[q][0..3]
       bf16x4 h, l;
 #pragma unroll
       for (int j = 0; j < 4; j++) { __bf16 x, y; split_bf16(v[q][j], x, y); h[j] = x; l[j] = y; }
@@ -147,10 +164,10 @@ __device__ __forceinline__ void store_panel_bf16(__bf16* hi, __bf16* lo, const f
 // ---------------------------------------------------------------------------
 // FP32 / FP64 staging: element-wise (these modes are bound by the slower MFMA).
 // ---------------------------------------------------------------------------
-template <int MODE, int SIDE>
+template <int MODE, int SIDE, int BM = SyrkCfg<MODE>::BM>
 __device__ __forceinline__ void load_panel_elem(const SyrkArgs& a, int64_t c0, int64_t k0, int64_t kend,
-                                                typename SyrkCfg<MODE>::AT (&v)[SyrkCfg<MODE>::BM * SyrkCfg<MODE>::BK / 256]) {
-  using Cfg = SyrkCfg<MODE>;
+                                                typename SyrkCfg<MODE, BM>::AT (&v)[BM * SyrkCfg<MODE, BM>::BK / 256]) {
+  using Cfg = SyrkCfg<MODE, BM>;
   using AT = typename Cfg::AT;
   constexpr int E = Cfg::BM * Cfg::BK / 256;
   const AT* A = (const AT*)a.A;
@@ -166,10 +183,10 @@ __device__ __forceinline__ void load_panel_elem(const SyrkArgs& a, int64_t c0, i
   }
 }
 
-template <int MODE, int SIDE>
-__device__ __forceinline__ void store_panel_elem(typename SyrkCfg<MODE>::AT* s,
-                                                 const typename SyrkCfg<MODE>::AT (&v)[SyrkCfg<MODE>::BM * SyrkCfg<MODE>::BK / 256]) {
-  using Cfg = SyrkCfg<MODE>;
+template <int MODE, int SIDE, int BM = SyrkCfg<MODE>::BM>
+__device__ __forceinline__ void store_panel_elem(typename SyrkCfg<MODE, BM>::AT* s,
+                                                 const typename SyrkCfg<MODE, BM>::AT (&v)[BM * SyrkCfg<MODE, BM>::BK / 256]) {
+  using Cfg = SyrkCfg<MODE, BM>;
   constexpr int E = Cfg::BM * Cfg::BK / 256;
 #pragma unroll
   for (int e = 0; e < E; e++) {
@@ -184,9 +201,9 @@ __device__ __forceinline__ void store_panel_elem(typename SyrkCfg<MODE>::AT* s,
 // ---------------------------------------------------------------------------
 // Partial-tile kernel
 // ---------------------------------------------------------------------------
-template <int MODE, int SIDE>
+template <int MODE, int SIDE, int BM_ = SyrkCfg<MODE>::BM>
 __device__ __forceinline__ void syrk_unit(const SyrkArgs& a, int s, int t, unsigned char* smem) {
-  using Cfg = SyrkCfg<MODE>;
+  using Cfg = SyrkCfg<MODE, BM_>;
   using AT = typename Cfg::AT;
   using OT = typename Cfg::OT;
   constexpr int BM = Cfg::BM, BK = Cfg::BK, LDK = Cfg::LDK;
@@ -200,26 +217,27 @@ __device__ __forceinline__ void syrk_unit(const SyrkArgs& a, int s, int t, unsig
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;  // 2 x 2 waves, each (BM/2) x (BM/2)
+  constexpr int WT = BM / 64;                 // 32 x 32 MFMA tiles per wave and dimension (BF16X3, FP32)
   OT* out = (OT*)a.partial + ((int64_t)s * a.T + t) * BM * BM;
   const int nk = (int)((kend - k0 + BK - 1) / BK);
 
   if constexpr (MODE == MODE_BF16X3) {
     // LDS: [stage][panel I/J][hi/lo][BM][LDK] bf16
     __bf16 (*lds)[2][2][BM * LDK] = reinterpret_cast<__bf16 (*)[2][2][BM * LDK]>(smem);
-    floatx16 acc[2][2];
+    floatx16 acc[WT][WT];
 #pragma unroll
-    for (int i = 0; i < 2; i++)
+    for (int i = 0; i < WT; i++)
 #pragma unroll
-      for (int j = 0; j < 2; j++)
+      for (int j = 0; j < WT; j++)
 #pragma unroll
         for (int e = 0; e < 16; e++) acc[i][j][e] = 0.0f;
 
     float vi[4][4], vj[4][4];
     if (nk > 0) {
-      load_panel_bf16<SIDE>(a, cI, k0, kend, vi);
-      if (!diag) load_panel_bf16<SIDE>(a, cJ, k0, kend, vj);
-      store_panel_bf16<SIDE>(lds[0][0][0], lds[0][0][1], vi);
-      if (!diag) store_panel_bf16<SIDE>(lds[0][1][0], lds[0][1][1], vj);
+      load_panel_bf16<SIDE, BM>(a, cI, k0, kend, vi);
+      if (!diag) load_panel_bf16<SIDE, BM>(a, cJ, k0, kend, vj);
+      store_panel_bf16<SIDE, BM>(lds[0][0][0], lds[0][0][1], vi);
+      if (!diag) store_panel_bf16<SIDE, BM>(lds[0][1][0], lds[0][1][1], vj);
     }
     __syncthreads();
     for (int kt = 0; kt < nk; kt++) {
@@ -227,8 +245,8 @@ __device__ __forceinline__ void syrk_unit(const SyrkArgs& a, int s, int t, unsig
       const bool more = kt + 1 < nk;
       if (more) {
         const int64_t kb = k0 + (int64_t)(kt + 1) * BK;
-        load_panel_bf16<SIDE>(a, cI, kb, kend, vi);
-        if (!diag) load_panel_bf16<SIDE>(a, cJ, kb, kend, vj);
+        load_panel_bf16<SIDE, BM>(a, cI, kb, kend, vi);
+        if (!diag) load_panel_bf16<SIDE, BM>(a, cJ, kb, kend, vj);
       }
       const __bf16* Ih = lds[cur][0][0];
       const __bf16* Il = lds[cur][0][1];
@@ -236,62 +254,62 @@ __device__ __forceinline__ void syrk_unit(const SyrkArgs& a, int s, int t, unsig
       const __bf16* Jl = diag ? Il : lds[cur][1][1];
 #pragma unroll
       for (int ks = 0; ks < BK; ks += 16) {
-        bf16x8 ah[2], al[2], bh[2], bl[2];
+        bf16x8 ah[WT], al[WT], bh[WT], bl[WT];
         const int kofs = ks + 8 * (lane >> 5);
 #pragma unroll
-        for (int i = 0; i < 2; i++) {
-          const int r = wm * 64 + i * 32 + (lane & 31);
+        for (int i = 0; i < WT; i++) {
+          const int r = wm * (BM / 2) + i * 32 + (lane & 31);
           ah[i] = *(const bf16x8*)(Ih + r * LDK + kofs);
           al[i] = *(const bf16x8*)(Il + r * LDK + kofs);
         }
 #pragma unroll
-        for (int j = 0; j < 2; j++) {
-          const int c = wn * 64 + j * 32 + (lane & 31);
+        for (int j = 0; j < WT; j++) {
+          const int c = wn * (BM / 2) + j * 32 + (lane & 31);
           bh[j] = *(const bf16x8*)(Jh + c * LDK + kofs);
           bl[j] = *(const bf16x8*)(Jl + c * LDK + kofs);
         }
 #pragma unroll
-        for (int i = 0; i < 2; i++)
+        for (int i = 0; i < WT; i++)
 #pragma unroll
-          for (int j = 0; j < 2; j++) {
+          for (int j = 0; j < WT; j++) {
             acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
             acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
             acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
           }
       }
       if (more) {
-        store_panel_bf16<SIDE>(lds[cur ^ 1][0][0], lds[cur ^ 1][0][1], vi);
-        if (!diag) store_panel_bf16<SIDE>(lds[cur ^ 1][1][0], lds[cur ^ 1][1][1], vj);
+        store_panel_bf16<SIDE, BM>(lds[cur ^ 1][0][0], lds[cur ^ 1][0][1], vi);
+        if (!diag) store_panel_bf16<SIDE, BM>(lds[cur ^ 1][1][0], lds[cur ^ 1][1][1], vj);
       }
       __syncthreads();
     }
     // 32x32 accumulator layout: item e -> row (e/4)*8 + (lane/32)*4 + e%4, col lane%32
 #pragma unroll
-    for (int i = 0; i < 2; i++)
+    for (int i = 0; i < WT; i++)
 #pragma unroll
-      for (int j = 0; j < 2; j++)
+      for (int j = 0; j < WT; j++)
 #pragma unroll
         for (int e = 0; e < 16; e++) {
-          const int r = wm * 64 + i * 32 + (e >> 2) * 8 + (lane >> 5) * 4 + (e & 3);
-          const int c = wn * 64 + j * 32 + (lane & 31);
+          const int r = wm * (BM / 2) + i * 32 + (e >> 2) * 8 + (lane >> 5) * 4 + (e & 3);
+          const int c = wn * (BM / 2) + j * 32 + (lane & 31);
           out[r * BM + c] = acc[i][j][e];
         }
   } else if constexpr (MODE == MODE_FP32) {
     float (*lds)[2][BM * LDK] = reinterpret_cast<float (*)[2][BM * LDK]>(smem);
     constexpr int E = BM * BK / 256;
-    floatx16 acc[2][2];
+    floatx16 acc[WT][WT];
 #pragma unroll
-    for (int i = 0; i < 2; i++)
+    for (int i = 0; i < WT; i++)
 #pragma unroll
-      for (int j = 0; j < 2; j++)
+      for (int j = 0; j < WT; j++)
 #pragma unroll
         for (int e = 0; e < 16; e++) acc[i][j][e] = 0.0f;
     float vi[E], vj[E];
     if (nk > 0) {
-      load_panel_elem<MODE, SIDE>(a, cI, k0, kend, vi);
-      if (!diag) load_panel_elem<MODE, SIDE>(a, cJ, k0, kend, vj);
-      store_panel_elem<MODE, SIDE>(lds[0][0], vi);
-      if (!diag) store_panel_elem<MODE, SIDE>(lds[0][1], vj);
+      load_panel_elem<MODE, SIDE, BM>(a, cI, k0, kend, vi);
+      if (!diag) load_panel_elem<MODE, SIDE, BM>(a, cJ, k0, kend, vj);
+      store_panel_elem<MODE, SIDE, BM>(lds[0][0], vi);
+      if (!diag) store_panel_elem<MODE, SIDE, BM>(lds[0][1], vj);
     }
     __syncthreads();
     for (int kt = 0; kt < nk; kt++) {
@@ -299,17 +317,17 @@ __device__ __forceinline__ void syrk_unit(const SyrkArgs& a, int s, int t, unsig
       const bool more = kt + 1 < nk;
       if (more) {
         const int64_t kb = k0 + (int64_t)(kt + 1) * BK;
-        load_panel_elem<MODE, SIDE>(a, cI, kb, kend, vi);
-        if (!diag) load_panel_elem<MODE, SIDE>(a, cJ, kb, kend, vj);
+        load_panel_elem<MODE, SIDE, BM>(a, cI, kb, kend, vi);
+        if (!diag) load_panel_elem<MODE, SIDE, BM>(a, cJ, kb, kend, vj);
       }
       const float* I = lds[cur][0];
       const float* J = diag ? I : lds[cur][1];
       // lane half h consumes k = 2*s + h for s = 0..15: stored at h*16 + s
       const int h = lane >> 5;
-      float av[2][16], bv[2][16];
+      float av[WT][16], bv[WT][16];
 #pragma unroll
-      for (int i = 0; i < 2; i++) {
-        const int r = wm * 64 + i * 32 + (lane & 31);
+      for (int i = 0; i < WT; i++) {
+        const int r = wm * (BM / 2) + i * 32 + (lane & 31);
 #pragma unroll
         for (int q = 0; q < 4; q++) {
           float4 f = *(const float4*)(I + r * LDK + h * 16 + 4 * q);
@@ -317,8 +335,8 @@ __device__ __forceinline__ void syrk_unit(const SyrkArgs& a, int s, int t, unsig
         }
       }
 #pragma unroll
-      for (int j = 0; j < 2; j++) {
-        const int c = wn * 64 + j * 32 + (lane & 31);
+      for (int j = 0; j < WT; j++) {
+        const int c = wn * (BM / 2) + j * 32 + (lane & 31);
 #pragma unroll
         for (int q = 0; q < 4; q++) {
           float4 f = *(const float4*)(J + c * LDK + h * 16 + 4 * q);
@@ -328,24 +346,24 @@ __device__ __forceinline__ void syrk_unit(const SyrkArgs& a, int s, int t, unsig
 #pragma unroll
       for (int ss = 0; ss < 16; ss++)
 #pragma unroll
-        for (int i = 0; i < 2; i++)
+        for (int i = 0; i < WT; i++)
 #pragma unroll
-          for (int j = 0; j < 2; j++)
+          for (int j = 0; j < WT; j++)
             acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i][ss], bv[j][ss], acc[i][j], 0, 0, 0);
       if (more) {
-        store_panel_elem<MODE, SIDE>(lds[cur ^ 1][0], vi);
-        if (!diag) store_panel_elem<MODE, SIDE>(lds[cur ^ 1][1], vj);
+        store_panel_elem<MODE, SIDE, BM>(lds[cur ^ 1][0], vi);
+        if (!diag) store_panel_elem<MODE, SIDE, BM>(lds[cur ^ 1][1], vj);
       }
       __syncthreads();
     }
 #pragma unroll
-    for (int i = 0; i < 2; i++)
+    for (int i = 0; i < WT; i++)
 #pragma unroll
-      for (int j = 0; j < 2; j++)
+      for (int j = 0; j < WT; j++)
 #pragma unroll
         for (int e = 0; e < 16; e++) {
-          const int r = wm * 64 + i * 32 + (e >> 2) * 8 + (lane >> 5) * 4 + (e & 3);
-          const int c = wn * 64 + j * 32 + (lane & 31);
+          const int r = wm * (BM / 2) + i * 32 + (e >> 2) * 8 + (lane >> 5) * 4 + (e & 3);
+          const int c = wn * (BM / 2) + j * 32 + (lane & 31);
           out[r * BM + c] = acc[i][j][e];
         }
   } else {

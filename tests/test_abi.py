@@ -81,6 +81,7 @@ int main(void) {
   Z(tsvd_opts)
   F(tsvd_tuning, gram_tile) F(tsvd_tuning, gram_chunks) F(tsvd_tuning, power_blocks) F(tsvd_tuning, team_kib)
   F(tsvd_tuning, group_kchunk) F(tsvd_tuning, sparse_row_bits) F(tsvd_tuning, sparse_col_bits) F(tsvd_tuning, power_path)
+  F(tsvd_tuning, group_tile) F(tsvd_tuning, group_kchunk_cls)
   Z(tsvd_tuning)
   F(tsvd_info, k_done) F(tsvd_info, iters) F(tsvd_info, lambda) F(tsvd_info, t_gram_ms) F(tsvd_info, h2d_bytes) F(tsvd_info, latency_ms)
   F(tsvd_info, t_stream_copy_ms) F(tsvd_info, t_stream_compute_ms) F(tsvd_info, t_stream_overlap_ms)
@@ -130,3 +131,12 @@ def test_struct_layouts_match_the_header(tmp_path):
             assert (desc.offset, desc.size) == (int(off), int(size)), name
         checked += 1
     assert checked >= 40
+
+
+def test_gram_class_boundaries():
+    """Gram-dimension classes of the batched Gram's unit shapes: 0 up to 128,
+    then one per power of two, the last class open-ended."""
+    assert P.GRAM_CLASSES == 8
+    cases = {1: 0, 128: 0, 129: 1, 256: 1, 257: 2, 512: 2, 1024: 3, 1025: 4, 4096: 5, 8192: 6, 8193: 7, 10**6: 7}
+    for d, c in cases.items():
+        assert P.gram_class(d) == c, d

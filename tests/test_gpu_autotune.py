@@ -53,3 +53,36 @@ def test_tune_batch(ctx, tuner):
     out = P.tsvd_dense_batched(ctx, probs, raise_errors=True)
     for (U, S, V, _), (Ur, Sr, Vr, _) in zip(out, ref):
         assert np.max(np.abs(S.cpu().numpy() - Sr.cpu().numpy()) / Sr.cpu().numpy()) < 1e-6
+
+
+def test_tune_gram_classes(ctx, tuner):
+    """Per-class batched-Gram unit shapes: the tuner picks each class's (tile
+    edge, chunk rows) among the candidates, apply_batch sets them beside the
+    batch class's team rule, and the results keep to FP32 rounding of the
+    default shapes."""
+    shapes = [(3000, 100), (4000, 257), (300, 2600), (2500, 1000), (5000, 700)]
+    chosen = tuner.tune_gram_classes(shapes, per_class=2)
+    assert set(chosen) == {P.gram_class(min(m, n)) for m, n in shapes}
+    for c, (tile, kc) in chosen.items():
+        K_max = max(max(m, n) for m, n in shapes if P.gram_class(min(m, n)) == c)
+        assert (tile, kc) in T.gram_unit_candidates(K_max)
+    assert P.get_tuning(ctx)["group_tile"] == [0] * P.GRAM_CLASSES  # restored
+    probs = []
+    for i, (m, n) in enumerate(shapes):
+        k = 3
+        dk = synth.dense_known(m, n, synth.spectrum_geometric(0.85, min(m, n)), seed=20 + i, dtype=np.float32)
+        st = synth.start_vectors(k, min(m, n), seed=30 + i)
+        probs.append(dict(A=to_dev(dk.A), k=k, eps=0.0, v0=to_dev(st), fixed_iters=[15] * k))
+    ref = P.tsvd_dense_batched(ctx, probs, raise_errors=True)
+    assert not tuner.apply_batch(shapes)  # no team-rule entry for this batch class, only class shapes
+    got = P.get_tuning(ctx)
+    for c, (tile, kc) in chosen.items():
+        assert (got["group_tile"][c], got["group_kchunk_cls"][c]) == (tile, kc)
+    out = P.tsvd_dense_batched(ctx, probs, raise_errors=True)
+    for (U, S, V, _), (Ur, Sr, Vr, _) in zip(out, ref):
+        assert np.max(np.abs(S.cpu().numpy() - Sr.cpu().numpy()) / Sr.cpu().numpy()) < 1e-6
+        for l in range(S.shape[0]):
+            assert line_angle(V[:, l].cpu().numpy(), Vr[:, l].cpu().numpy()) < 1e-4
+    t2 = T.Tuner(ctx, tuner.path)
+    ct = t2.class_tuning()
+    assert {c: (ct["group_tile"][c], ct["group_kchunk_cls"][c]) for c in chosen} == chosen

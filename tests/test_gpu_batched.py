@@ -201,3 +201,59 @@ def test_batched_random_mix_team_rules(tuned, team_kib):
             k = p["k"]
             assert info["status"] == "TSVD_OK"
             assert np.max(np.abs(S.cpu().numpy() - dk.s[:k]) / dk.s[:k]) < 1e-6
+
+
+# one or two shapes per Gram-dimension class 0..5, both sides, ragged tiles
+CLASS_MIX = [(3000, 100, 3), (90, 2500, 2), (4000, 257, 4), (200, 5000, 3), (2500, 1000, 4), (700, 1500, 3),
+             (6000, 2100, 2), (129, 129, 2)]
+
+
+@pytest.mark.parametrize("gram", ["bf16x3", "fp32"])
+def test_batched_tile_edge_same_bits(tuned, gram):
+    """The batched Gram's tile edge changes no bit of any result: every Gram
+    entry sums the same contraction steps in the same order whichever tile
+    holds it (64-wide and 128-wide tiles in every class, both sides, ragged
+    edges)."""
+    ctx = tuned
+    probs = []
+    for i, (m, n, k) in enumerate(CLASS_MIX):
+        dk, st = make_problem(m, n, k, gram, seed=300 + i)
+        probs.append(dict(A=to_dev(dk.A), k=k, eps=0.0, v0=to_dev(st), gram=gram, fixed_iters=[12] * k))
+    outs = []
+    for tile in (64, 128):
+        P.set_tuning(ctx, group_tile=[tile] * P.GRAM_CLASSES)
+        outs.append(P.tsvd_dense_batched(ctx, probs, raise_errors=True))
+    for (m, n, k), a, b in zip(CLASS_MIX, outs[0], outs[1]):
+        for x, y in zip(a[:3], b[:3]):
+            assert torch_equal(x, y), (m, n, P.gram_class(min(m, n)))
+
+
+def test_batched_class_chunk_alone_equals_mixed(tuned):
+    """A class's own chunk length (group_kchunk_cls) applies per problem: a
+    problem gives the same bits alone and in a mix, and the chunk length
+    changes only FP32 rounding (sigma within 1e-6 of the default's)."""
+    ctx = tuned
+    probs = []
+    for i, (m, n, k) in enumerate(CLASS_MIX[:6]):
+        dk, st = make_problem(m, n, k, "bf16x3", seed=400 + i)
+        probs.append(dict(A=to_dev(dk.A), k=k, eps=0.0, v0=to_dev(st), gram="bf16x3", fixed_iters=[20] * k))
+    ref = P.tsvd_dense_batched(ctx, probs, raise_errors=True)
+    cls = P.gram_class(1000)  # the (2500, 1000) problem's class
+    kc = [0] * P.GRAM_CLASSES
+    kc[cls] = 256
+    P.set_tuning(ctx, group_kchunk_cls=kc, group_tile={cls: 64})
+    mixed = P.tsvd_dense_batched(ctx, probs, raise_errors=True)
+    alone = P.tsvd_dense_batched(ctx, [probs[4]], raise_errors=True)[0]
+    for x, y in zip(mixed[4][:3], alone[:3]):
+        assert torch_equal(x, y)
+    Sm, Sr = mixed[4][1].cpu().numpy(), ref[4][1].cpu().numpy()
+    assert np.max(np.abs(Sm - Sr) / Sr) < 1e-6
+    for (m, n, k), a, b in zip(CLASS_MIX[:6], mixed, ref):
+        if P.gram_class(min(m, n)) != cls:
+            for x, y in zip(a[:3], b[:3]):
+                assert torch_equal(x, y), (m, n)
+
+
+def torch_equal(x, y):
+    import torch
+    return bool(torch.equal(x, y))
