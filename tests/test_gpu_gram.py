@@ -115,4 +115,12 @@ def test_tuning_rejects_bad_values(ctx):
         P.set_tuning(ctx, sparse_row_bits=12)
     with pytest.raises(P.TsvdError):
         P.set_tuning(ctx, sparse_row_bits=11, sparse_col_bits=22)
-    assert P.get_tuning(ctx) == {f: 0 for f in P.TUNING_FIELDS}
+    with pytest.raises(P.TsvdError):
+        P.set_tuning(ctx, group_tile={2: 256})
+    with pytest.raises(P.TsvdError):
+        P.set_tuning(ctx, group_kchunk_cls={7: 16})
+    with pytest.raises(ValueError):
+        P.set_tuning(ctx, group_tile={8: 64})
+    zero = {f: 0 for f in P.TUNING_FIELDS}
+    zero.update(group_tile=[0] * P.GRAM_CLASSES, group_kchunk_cls=[0] * P.GRAM_CLASSES)
+    assert P.get_tuning(ctx) == zero
