@@ -96,7 +96,9 @@ TRAFFIC_SOURCES = {
     # key -> (file under csrc/, marker that ends the hashed part, or None for the
     # whole file); whole files, since the host-side plans set the launch shapes
     "power.hip": ("power.hip", None),
+    "exchange.h": ("exchange.h", None),
     "syrk.hip": ("syrk.hip", None),
+    "syrk_dev.h": ("syrk_dev.h", None),
     "common.h": ("common.h", None),
 }
 
