@@ -979,7 +979,8 @@ def main():
     if "serve" in legs:
         progress("serving leg")
         sa = argparse.Namespace(**vars(a))
-        sa.window, sa.warm, sa.pool, sa.pool_loc = a.leg_window, 2.0, 24, "host"
+        # the serving workload's own pool (48 matrices of the mix) in pinned host memory
+        sa.window, sa.warm, sa.pool, sa.pool_loc = a.leg_window, 2.0, 48, "host"
         r = serve_run(sa)
         out["legs"]["serve"] = {k_: r[k_] for k_ in ("config", "p50_ms", "p99_ms", "max_ms", "requests", "offered_rate",
                                                       "achieved_rate", "all_ok", "sigma_rel_err_max", "meets_1e-6",
