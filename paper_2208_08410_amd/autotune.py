@@ -249,15 +249,15 @@ class Tuner:
         for m, n in shapes:
             by_cls.setdefault(gram_class(min(m, n)), []).append((int(m), int(n)))
         saved = get_tuning(self.ctx)
-        gen = torch.Generator(device="cpu").manual_seed(int(seed))
         dev = torch.device("cuda", self.ctx.device)
+        gen = torch.Generator(device=dev).manual_seed(int(seed))
         chosen = {}
         for c in sorted(by_cls):
             sub = by_cls[c][:per_class]
             probs = []
             for m, n in sub:
-                A = torch.randn((m, n), generator=gen, dtype=torch.float32).to(dev)
-                v0 = torch.randn((1, min(m, n)), generator=gen, dtype=torch.float64).to(dev)
+                A = torch.randn((m, n), generator=gen, dtype=torch.float32, device=dev)
+                v0 = torch.randn((1, min(m, n)), generator=gen, dtype=torch.float64, device=dev)
                 probs.append({"A": A, "k": 1, "eps": 0.0, "v0": v0, "fixed_iters": [1], "gram": "bf16x3"})
             K_max = max(max(m, n) for m, n in sub)
             trials = []
