@@ -40,8 +40,10 @@ int gram_class(int64_t d) {
   return c;
 }
 
-// library choice of the tile edge per class: 64 below d = 256, where a
-// 128 edge would compute up to twice the triangle's area
+// library choice of the tile edge per class: 64 up to d = 128 (one 128-edge
+// diagonal tile would compute the whole 128 x 128 square in one unit; three
+// 64-edge triangle tiles compute three quarters of it in three units), 128
+// above (twice the MFMA work per panel load of a 64-edge tile)
 int default_tile(int cls) { return cls == 0 ? 64 : 128; }
 
 // workgroups a problem's power iteration runs on: enough to hold its Gram at
