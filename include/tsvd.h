@@ -177,7 +177,7 @@ typedef struct {
      bit (every Gram entry sums the same contraction steps in the same order); the chunk length sets
      the split-K order of the FP32 sums, per problem, so a problem still gives the same bits alone and
      in any mix. */
-  int32_t group_tile[TSVD_GRAM_CLASSES];       /* tile edge of class c: 0 = library choice, 64 or 128 */
+  int32_t group_tile[TSVD_GRAM_CLASSES];       /* tile edge of class c: 0 = library choice (128), 64 or 128 */
   int32_t group_kchunk_cls[TSVD_GRAM_CLASSES]; /* contraction rows per unit of class c: 0 = group_kchunk;
                                                   range [32, 2^20] */
 } tsvd_tuning;
