@@ -673,7 +673,7 @@ def sparse_main(a):
     roof_sp = {"kernel": "spmv_tiles_kernel<float> (A x)", "bound": "l2 gather", "achieved": gach, "peak": gpeak,
                "unit": "G gathers/s", "frac": (gach / gpeak) if gpeak else None, "traffic": None,
                "note": "one 4-byte x gather per nonzero; peak = random gathers over a set the size of one column "
-                       "slice of x (tsvd_bench gather, same box)"}
+                       "slice of x (tsvd_bench gather, same GPU)"}
     out = {
         "metric": METRIC,
         "value": pair / (per_iter * 1e-3) / 1e9,

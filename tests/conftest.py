@@ -14,7 +14,7 @@ def pytest_configure(config):
 
 
 def pytest_collection_modifyitems(config, items):
-    # GPU tests run in one process on the box; nothing to reorder here beyond marking.
+    # GPU tests run in one process; nothing to reorder here beyond marking.
     pass
 
 
