@@ -101,14 +101,17 @@ tsvd_status batch_plan(tsvd_ctx* ctx, int count, const tsvd_problem* probs, Batc
       return fail(ctx, TSVD_ERR_UNSUPPORTED, "problem %d: Gram dimension %lld too large for the batched path", i,
                   (long long)p.d);
     // Gram work units: the class's tile edge, split-K chunks of about the
-    // class's contraction rows, at most 4096 partial tiles per problem
+    // class's contraction rows, the chunk count capped so that the partials
+    // would fill at most 4096 tiles of edge 128 (the same bytes for edge 64):
+    // the chunking, and so every result bit, does not depend on the edge
     const int cls = gram_class(p.d);
     p.bm = ctx->tuning.group_tile[cls] > 0 ? ctx->tuning.group_tile[cls] : default_tile(cls);
     const int64_t kc_target = ctx->tuning.group_kchunk_cls[cls] > 0 ? ctx->tuning.group_kchunk_cls[cls] : kc_default;
     p.nt = (int)((p.d + p.bm - 1) / p.bm);
     p.T = p.nt * (p.nt + 1) / 2;
+    const int64_t nt128 = (p.d + 127) / 128, T128 = nt128 * (nt128 + 1) / 2;
     int64_t S = std::max<int64_t>(1, (p.K + kc_target / 2) / kc_target);
-    S = std::min<int64_t>(S, std::max<int64_t>(1, 4096 / p.T));
+    S = std::min<int64_t>(S, std::max<int64_t>(1, 4096 / T128));
     int64_t kchunk = (p.K + S - 1) / S;
     kchunk = (kchunk + 31) / 32 * 32;
     p.S = (int)((p.K + kchunk - 1) / kchunk);

@@ -203,9 +203,11 @@ def test_batched_random_mix_team_rules(tuned, team_kib):
             assert np.max(np.abs(S.cpu().numpy() - dk.s[:k]) / dk.s[:k]) < 1e-6
 
 
-# one or two shapes per Gram-dimension class 0..5, both sides, ragged tiles
+# one or two shapes per Gram-dimension class 0..5, both sides, ragged tiles;
+# the last one has enough contraction rows for the cap on its chunk count to
+# bind (24 x 24 tiles of edge 128)
 CLASS_MIX = [(3000, 100, 3), (90, 2500, 2), (4000, 257, 4), (200, 5000, 3), (2500, 1000, 4), (700, 1500, 3),
-             (6000, 2100, 2), (129, 129, 2)]
+             (6000, 2100, 2), (129, 129, 2), (40000, 3000, 2)]
 
 
 @pytest.mark.parametrize("gram", ["bf16x3", "fp32"])
@@ -214,11 +216,14 @@ def test_batched_tile_edge_same_bits(tuned, gram):
     entry sums the same contraction steps in the same order whichever tile
     holds it (64-wide and 128-wide tiles in every class, both sides, ragged
     edges)."""
+    import torch
     ctx = tuned
     probs = []
+    g = torch.Generator(device="cuda:0").manual_seed(300)
     for i, (m, n, k) in enumerate(CLASS_MIX):
-        dk, st = make_problem(m, n, k, gram, seed=300 + i)
-        probs.append(dict(A=to_dev(dk.A), k=k, eps=0.0, v0=to_dev(st), gram=gram, fixed_iters=[12] * k))
+        A = torch.randn((m, n), generator=g, dtype=torch.float32, device="cuda:0")
+        st = synth.start_vectors(k, min(m, n), seed=300 + i)
+        probs.append(dict(A=A, k=k, eps=0.0, v0=to_dev(st), gram=gram, fixed_iters=[12] * k))
     outs = []
     for tile in (64, 128):
         P.set_tuning(ctx, group_tile=[tile] * P.GRAM_CLASSES)
