@@ -81,12 +81,12 @@ typedef struct {
                               right branch, m for the left): row l is the N(0, I) start vector of
                               triplet l (Algorithm 2 draws one per call).  Required. */
   int32_t gram;            /* tsvd_gram */
-  int64_t rows_per_block;  /* contraction rows per Gram chunk (in HBM) or per streamed batch
-                              (pinned host); 0 = library default */
+  int64_t rows_per_block;  /* contraction rows (columns, for m < n) per Gram chunk (in HBM) or per
+                              streamed batch (pinned host); 0 = library default */
   int64_t hbm_budget;      /* device bytes the call may allocate for workspace; 0 = no limit */
   int32_t branch;          /* 0: m >= n iterates on v (A^T A); 1: m > n as printed in Algorithm 1 */
   int32_t queue_depth;     /* device buffers in the host->device batch pipelines, 1..16 (default 2; the
-                              pinned-A Gram pipeline takes at least 2): A's row batches, sparse tile
+                              pinned-A Gram pipeline takes at least 2): A's row (or column) batches, sparse tile
                               batches, and the factor batches below */
   int32_t method;          /* dense A only (tsvd_method): how Algorithm 2's product is applied */
   int32_t factor_loc;      /* implicit paths (sparse A, method IMPLICIT): where the iterated factor X lives
@@ -125,7 +125,7 @@ typedef struct {
   int64_t workspace_bytes; /* device workspace the call used */
   int64_t h2d_bytes;       /* bytes copied host -> device (pinned-host input) */
   double latency_ms;       /* server requests: submission -> completion, host clock; else 0 */
-  double t_stream_copy_ms;    /* pinned-host A, Gram pass: time the copy stream spent copying row batches
+  double t_stream_copy_ms;    /* pinned-host A, Gram pass: time the copy stream spent copying batches
                                  (sum of per-batch HIP event intervals); else 0 */
   double t_stream_compute_ms; /* the same pass: time the compute stream spent in the batches' Grams */
   double t_stream_overlap_ms; /* time during which both ran at once (intersection of the two streams'
@@ -243,8 +243,10 @@ tsvd_status tsvd_finish_dense_noalloc(tsvd_ctx* ctx, const void* A, int32_t dtyp
  * ------------------------------------------------------------------------- */
 
 /* A: dtype, m x n row-major (lda); loc DEVICE (in HBM) or PINNED_HOST (pinned
- * host memory, streamed to the device in row batches through a
- * double-buffered copy pipeline; FP32 only).  U: DEVICE FP64 m x k
+ * host memory, streamed to the device along the Gram's contraction through a
+ * double-buffered copy pipeline: row batches for m >= n, pitched column
+ * batches for m < n; FP32 only; the implicit method streams row batches and
+ * takes m >= n only).  U: DEVICE FP64 m x k
  * column-major (ldu); S: DEVICE FP64 k; V: DEVICE FP64 n x k column-major
  * (ldv).  Triplets past info->k_done are zero.  Synchronises `stream`.
  * Returns OK, NOT_CONVERGED (outputs filled), NONFINITE, INVALID_ARG,

@@ -490,7 +490,8 @@ def tsvd_dense(ctx: Context, A, k, eps, v0, max_iter=10000, fixed_iters=None, gr
                hbm_budget=0, branch=0, stream=None, raise_not_converged=False, queue_depth=2, method="auto",
                factor="device", factor_batches=1):
     """Whole t-SVD of a dense A.  A is a device tensor (resident in HBM) or a
-    pinned host tensor (``A.is_pinned()``: streamed in row batches).  method:
+    pinned host tensor (``A.is_pinned()``: streamed in row batches, or in
+    column batches when m < n).  method:
     "gram" (form the Gram once), "implicit" (A^T (A x) every iteration) or
     "auto".  factor="host" keeps the iterated factor (V on the right branch,
     U on the left) in pinned host memory, batched to the device in

@@ -642,18 +642,19 @@ tsvd_status dense_implicit(tsvd_ctx* ctx, const void* A, int32_t dtype, int32_t 
 }
 
 // Dense t-SVD of an FP32 A held in pinned host memory (Algorithm 3's
-// out-of-memory batching).  Rows are streamed in batches through
-// `queue_depth` device buffers: the copy stream fills buffer b % Q while the
-// compute stream runs the Gram (pass 1) or the FP64 finishing product (pass 2)
-// on the previous batch; events order reuse.  The power iteration runs on the
-// device-resident Gram between the passes, overlapped with the first copies of
-// pass 2.  auto_method: fall back to the implicit product when the Gram's
-// workspace does not fit.
+// out-of-memory batching).  A is streamed in batches along the Gram's
+// contraction: row batches for the A^T A branch, column batches (pitched 2-D
+// copies) for the A A^T branch, through `queue_depth` device buffers: the copy
+// stream fills buffer b % Q while the compute stream runs the Gram (pass 1) or
+// the FP64 finishing product (pass 2: the rows of U, or of V, that the batch
+// owns) on the previous batch; events order reuse.  The power iteration runs
+// on the device-resident Gram between the passes, overlapped with the first
+// copies of pass 2.  auto_method: fall back to the implicit product when the
+// Gram's workspace does not fit.
 tsvd_status dense_pinned(tsvd_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t lda, const tsvd_opts* o, int k,
                          int mode, bool auto_method, double* U, int64_t ldu, double* S, double* V, int64_t ldv,
                          tsvd_info* info, hipStream_t s) {
-  if (!right_side(m, n, o->branch))
-    return fail(ctx, TSVD_ERR_UNSUPPORTED, "pinned-host input needs the A^T A branch (m >= n)");
+  const bool right = right_side(m, n, o->branch);
   hipPointerAttribute_t attr;
   if (hipPointerGetAttributes(&attr, A) != hipSuccess || attr.type != hipMemoryTypeHost) {
     (void)hipGetLastError();
@@ -661,27 +662,29 @@ tsvd_status dense_pinned(tsvd_ctx* ctx, const float* A, int64_t m, int64_t n, in
   }
   const int Q = o->queue_depth >= 2 ? o->queue_depth : 2;
   if (Q > 16) return fail(ctx, TSVD_ERR_INVALID_ARG, "queue_depth > 16");
-  const int64_t d = n;
+  // d: Gram dimension; L: length of the streamed (contraction) dimension
+  const int64_t d = right ? n : m, L = right ? m : n;
   const int64_t ldb = (d + 3) & ~3;
   const bool explicit_rows = o->rows_per_block > 0;
-  // batch rows: rows_per_block rounded up to a multiple of 128 (the finishing
-  // pass's row tile), or 4 GiB worth of rows rounded down to one
-  int64_t R = explicit_rows ? ((o->rows_per_block + 127) / 128) * 128 : (((int64_t)4 << 30) / (n * 4)) / 128 * 128;
+  // batch length: rows_per_block rounded up to a multiple of 128 (the
+  // finishing pass's row tile), or 4 GiB worth of rows (columns) rounded down
+  // to one
+  int64_t R = explicit_rows ? ((o->rows_per_block + 127) / 128) * 128 : (((int64_t)4 << 30) / (d * 4)) / 128 * 128;
   if (R < 128) R = 128;
-  if (R > m) R = m;
-  const int64_t nbatch = (m + R - 1) / R;
+  if (R > L) R = L;
+  const int64_t nbatch = (L + R - 1) / R;
   // Gram plan per batch (one chunk per batch when the batch size is given, so
   // the result is bitwise that of the in-HBM path with the same rows_per_block)
   SyrkPlan sp_full, sp_last;
-  const int64_t last_rows = m - (nbatch - 1) * R;
+  const int64_t last_rows = L - (nbatch - 1) * R;
   syrk_plan(mode, d, R, explicit_rows ? R : 0, ctx->num_cu, &sp_full, ctx->tuning.gram_tile, ctx->tuning.gram_chunks);
   syrk_plan(mode, d, last_rows, explicit_rows ? last_rows : 0, ctx->num_cu, &sp_last, ctx->tuning.gram_tile,
             ctx->tuning.gram_chunks);
   const size_t part_bytes = sp_full.partial_bytes > sp_last.partial_bytes ? sp_full.partial_bytes : sp_last.partial_bytes;
   PowerPlan pp;
   const bool onchip = plan_onchip(ctx, 4, d, k, &pp);
-  const int64_t tiles_total = (m + 127) / 128 + nbatch;  // finish row tiles, one partial tile per batch at most
-  const size_t buf_bytes = align256((size_t)R * n * 4);
+  const int64_t tiles_total = (L + 127) / 128 + nbatch;  // finish row tiles, one partial tile per batch at most
+  const size_t buf_bytes = align256((size_t)R * d * 4);
   const size_t b_bytes = align256((size_t)d * ldb * 4);
   const size_t ssq_bytes = align256((size_t)(tiles_total + 2) * k * 8);
   const size_t need =
@@ -715,13 +718,17 @@ tsvd_status dense_pinned(tsvd_ctx* ctx, const float* A, int64_t m, int64_t n, in
   }
   hipStream_t cs = ctx->copy_stream;
   int rc = 0;
+  // batch b: rows [r0, r0 + len) of A (a len x n block, pitch n) or its
+  // columns [r0, r0 + len) (an m x len block, pitch len)
   auto copy_batch = [&](int64_t b, int slot, bool wait_slot) -> int {
     const int64_t r0 = b * R;
-    const int64_t rows = (b == nbatch - 1) ? last_rows : R;
+    const int64_t len = (b == nbatch - 1) ? last_rows : R;
     if (wait_slot && hipStreamWaitEvent(cs, consumed[slot], 0) != hipSuccess) return TSVD_ERR_HIP;
-    if (hipMemcpy2DAsync(buf[slot], (size_t)n * 4, A + r0 * lda, (size_t)lda * 4, (size_t)n * 4, (size_t)rows,
-                         hipMemcpyHostToDevice, cs) != hipSuccess)
-      return TSVD_ERR_HIP;
+    const hipError_t e = right ? hipMemcpy2DAsync(buf[slot], (size_t)n * 4, A + r0 * lda, (size_t)lda * 4, (size_t)n * 4,
+                                                  (size_t)len, hipMemcpyHostToDevice, cs)
+                               : hipMemcpy2DAsync(buf[slot], (size_t)len * 4, A + r0, (size_t)lda * 4, (size_t)len * 4,
+                                                  (size_t)m, hipMemcpyHostToDevice, cs);
+    if (e != hipSuccess) return TSVD_ERR_HIP;
     if (hipEventRecord(copied[slot], cs) != hipSuccess) return TSVD_ERR_HIP;
     return 0;
   };
@@ -750,7 +757,7 @@ tsvd_status dense_pinned(tsvd_ctx* ctx, const float* A, int64_t m, int64_t n, in
     cleanup_all();
     return fail(ctx, TSVD_ERR_HIP, "clear outputs");
   }
-  // ---- pass 1: B = sum_b A_b^T A_b
+  // ---- pass 1: B = sum_b A_b^T A_b (or A_b A_b^T for column batches)
   for (int64_t b = 0; b < nbatch && !rc; b++) {
     const int slot = (int)(b % Q);
     if (b >= Q && hipStreamWaitEvent(cs, consumed[slot], 0) != hipSuccess) { rc = TSVD_ERR_HIP; break; }
@@ -758,10 +765,12 @@ tsvd_status dense_pinned(tsvd_ctx* ctx, const float* A, int64_t m, int64_t n, in
     if ((rc = copy_batch(b, slot, false))) break;
     if (!tev.empty() && hipEventRecord(tev[4 * b + 1], cs) != hipSuccess) { rc = TSVD_ERR_HIP; break; }
     if (hipStreamWaitEvent(s, copied[slot], 0) != hipSuccess) { rc = TSVD_ERR_HIP; break; }
-    const int64_t rows = (b == nbatch - 1) ? last_rows : R;
+    const int64_t len = (b == nbatch - 1) ? last_rows : R;
     const SyrkPlan& sp = (b == nbatch - 1) ? sp_last : sp_full;
     if (!tev.empty() && hipEventRecord(tev[4 * b + 2], s) != hipSuccess) { rc = TSVD_ERR_HIP; break; }
-    if ((rc = syrk_launch(mode, 0, buf[slot], rows, n, n, sp, partial, B, ldb, b > 0 ? 1 : 0, s))) break;
+    rc = right ? syrk_launch(mode, 0, buf[slot], len, n, n, sp, partial, B, ldb, b > 0 ? 1 : 0, s)
+               : syrk_launch(mode, 1, buf[slot], m, len, len, sp, partial, B, ldb, b > 0 ? 1 : 0, s);
+    if (rc) break;
     if (!tev.empty() && hipEventRecord(tev[4 * b + 3], s) != hipSuccess) { rc = TSVD_ERR_HIP; break; }
     if (hipEventRecord(consumed[slot], s) != hipSuccess) { rc = TSVD_ERR_HIP; break; }
   }
@@ -772,7 +781,8 @@ tsvd_status dense_pinned(tsvd_ctx* ctx, const float* A, int64_t m, int64_t n, in
   for (int64_t b = 0; b < pre && !rc; b++) rc = copy_batch(b, (int)(b % Q), true);
   if (rc) { cleanup(); return from_internal(ctx, rc, "prefetch"); }
   PhaseResult pr;
-  st = power_phase(ctx, bump, onchip, pp, B, 0, d, ldb, k, o, V, ldv, &pr, s);
+  st = right ? power_phase(ctx, bump, onchip, pp, B, 0, d, ldb, k, o, V, ldv, &pr, s)
+             : power_phase(ctx, bump, onchip, pp, B, 0, d, ldb, k, o, U, ldu, &pr, s);
   if (st) {
     (void)hipStreamSynchronize(cs);
     cleanup_all();
@@ -780,20 +790,25 @@ tsvd_status dense_pinned(tsvd_ctx* ctx, const float* A, int64_t m, int64_t n, in
   }
   hipEventRecord(ctx->ev[2], s);
   const int kd = pr.kd;
-  // ---- pass 2: U = A V (FP64), column sums of squares per row tile
+  // ---- pass 2: U = A V (or V = A^T U) in FP64, the batch's rows of it;
+  // column sums of squares per row tile
   int64_t tile_off = 0;
   for (int64_t b = 0; b < nbatch && !rc && kd > 0; b++) {
     const int slot = (int)(b % Q);
     if (b >= pre && (rc = copy_batch(b, slot, true))) break;
     if (hipStreamWaitEvent(s, copied[slot], 0) != hipSuccess) { rc = TSVD_ERR_HIP; break; }
     const int64_t r0 = b * R;
-    const int64_t rows = (b == nbatch - 1) ? last_rows : R;
-    if ((rc = finish_gemm_launch(0, 0, buf[slot], rows, n, n, V, ldv, kd, U + r0, ldu, ssq + tile_off * kd, s))) break;
-    tile_off += (rows + 127) / 128;
+    const int64_t len = (b == nbatch - 1) ? last_rows : R;
+    rc = right ? finish_gemm_launch(0, 0, buf[slot], len, n, n, V, ldv, kd, U + r0, ldu, ssq + tile_off * kd, s)
+               : finish_gemm_launch(0, 1, buf[slot], m, len, len, U, ldu, kd, V + r0, ldv, ssq + tile_off * kd, s);
+    if (rc) break;
+    tile_off += (len + 127) / 128;
     if (hipEventRecord(consumed[slot], s) != hipSuccess) { rc = TSVD_ERR_HIP; break; }
   }
   if (!rc && kd > 0) rc = finish_sigma_launch(ssq, tile_off, kd, S, s);
-  if (!rc && kd > 0) rc = finish_scale_sign_launch(U, ldu, m, S, V, ldv, n, U, ldu, m, kd, 1, ssq + tiles_total * k, s);
+  if (!rc && kd > 0)
+    rc = right ? finish_scale_sign_launch(U, ldu, m, S, V, ldv, n, U, ldu, m, kd, 1, ssq + tiles_total * k, s)
+               : finish_scale_sign_launch(V, ldv, n, S, V, ldv, n, U, ldu, m, kd, 1, ssq + tiles_total * k, s);
   hipEventRecord(ctx->ev[3], s);
   if (!rc && (hipStreamSynchronize(s) != hipSuccess || hipStreamSynchronize(cs) != hipSuccess)) rc = TSVD_ERR_HIP;
   double copy_ms = 0.0, comp_ms = 0.0, overlap_ms = 0.0;
@@ -813,7 +828,7 @@ tsvd_status dense_pinned(tsvd_ctx* ctx, const float* A, int64_t m, int64_t n, in
   }
   cleanup_all();
   if (rc) return from_internal(ctx, rc, "pinned finish pass");
-  fill_info(info, pr, k, true, ctx, need, (int64_t)(m * n * 4) * (kd > 0 ? 2 : 1));
+  fill_info(info, pr, k, right, ctx, need, (int64_t)(m * n * 4) * (kd > 0 ? 2 : 1));
   if (info) {
     info->t_stream_copy_ms = copy_ms;
     info->t_stream_compute_ms = comp_ms;

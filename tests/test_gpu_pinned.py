@@ -55,16 +55,55 @@ def test_pinned_batches_vs_oracle(ctx, rpb, q):
         assert line_angle(U[:, l], Ur[:, l]) < 1e-4
 
 
-def test_pinned_rejects_pageable_and_left_branch(ctx):
+def test_pinned_rejects_pageable_and_implicit_left_branch(ctx):
     import torch
     A = torch.from_numpy(synth.gaussian_dense(100, 50, seed=1))
     st = to_dev(synth.start_vectors(2, 50, seed=1))
     with pytest.raises(ValueError):
         P.tsvd_dense(ctx, A, 2, 1e-8, st)  # pageable memory is refused by the binding
+    # the implicit product streams row batches only (the A^T A branch)
     Aw = pinned(synth.gaussian_dense(50, 100, seed=1))
     with pytest.raises(P.TsvdError) as e:
-        P.tsvd_dense(ctx, Aw, 2, 1e-8, to_dev(synth.start_vectors(2, 50, seed=1)))
+        P.tsvd_dense(ctx, Aw, 2, 1e-8, to_dev(synth.start_vectors(2, 50, seed=1)), method="implicit")
     assert e.value.status == P.UNSUPPORTED
+
+
+@pytest.mark.parametrize("cpb,q,gram", [(3072, 2, "bf16x3"), (2048, 3, "fp32"), (768, 2, "bf16x3")])
+def test_pinned_left_branch_bitwise_equals_device(ctx, cpb, q, gram):
+    """m < n (the A A^T branch, Eq. 3): A streams in column batches of cpb
+    (pitched copies, a multiple of 128) with one Gram chunk per batch, and
+    gives the same bits as the in-HBM path with the same column blocking; the
+    last batch is ragged."""
+    m, n, k = 384, 20000, 6
+    dk = synth.dense_known(m, n, synth.spectrum_geometric(0.9, m), seed=13, dtype=np.float32)
+    st = to_dev(synth.start_vectors(k, m, seed=12))
+    Ud, Sd, Vd, infd = P.tsvd_dense(ctx, to_dev(dk.A), k, 1e-9, st, gram=gram, rows_per_block=cpb)
+    Up, Sp, Vp, infp = P.tsvd_dense(ctx, pinned(dk.A), k, 1e-9, st, gram=gram, rows_per_block=cpb, queue_depth=q)
+    assert not infp["branch_right"] and not infd["branch_right"]
+    assert infp["h2d_bytes"] == 2 * m * n * 4
+    assert infp["iters"] == infd["iters"]
+    assert np.array_equal(Sp.cpu().numpy(), Sd.cpu().numpy())
+    assert np.array_equal(Vp.cpu().numpy(), Vd.cpu().numpy())
+    assert np.array_equal(Up.cpu().numpy(), Ud.cpu().numpy())
+
+
+@pytest.mark.parametrize("cpb,q", [(0, 2), (2500, 3)])
+def test_pinned_left_branch_vs_oracle(ctx, cpb, q):
+    """m < n streamed in column batches (one batch, or 12 through 3 buffers):
+    sigma, u and v against the FP64 oracle's left branch in trajectory mode."""
+    m, n, k, eps = 256, 30000, 5, 1e-9
+    dk = synth.dense_known(m, n, synth.spectrum_geometric(0.9, m), seed=14, dtype=np.float32)
+    st = synth.start_vectors(k, m, seed=15)
+    ref = O.tsvd_gram(dk.A, eps, k, st)
+    U, S, V, info = P.tsvd_dense(ctx, pinned(dk.A), k, eps, to_dev(st), fixed_iters=ref.iters, rows_per_block=cpb,
+                                 queue_depth=q)
+    assert info["h2d_bytes"] == 2 * m * n * 4
+    S = S.cpu().numpy(); V = V.cpu().numpy(); U = U.cpu().numpy()
+    assert np.max(np.abs(S - ref.S) / ref.S) < 1e-6
+    Ur, Vr = O.canonical(ref.U, ref.V)
+    for l in range(k):
+        assert line_angle(V[:, l], Vr[:, l]) < 1e-4
+        assert line_angle(U[:, l], Ur[:, l]) < 1e-4
 
 
 def test_pinned_stream_timing_is_consistent(ctx):
