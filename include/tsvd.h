@@ -105,7 +105,8 @@ typedef struct {
  *           kernel, else as a host-driven loop of HBM-streamed B x products.
  * IMPLICIT: never form B: every iteration applies A^T (A x) (or A (A^T x)) as
  *           two mat-vecs over A (Equation 2 evaluated right to left); A in
- *           pinned host memory is then streamed once per iteration (m >= n).
+ *           pinned host memory is then streamed once per iteration (row
+ *           batches for m >= n, pitched column batches for m < n).
  * AUTO:     GRAM when its workspace (B, split-K partials, finish sums, plus the
  *           row-batch buffers for pinned A) fits hbm_budget and the device's
  *           free memory, else IMPLICIT.                                       */
@@ -245,8 +246,7 @@ tsvd_status tsvd_finish_dense_noalloc(tsvd_ctx* ctx, const void* A, int32_t dtyp
 /* A: dtype, m x n row-major (lda); loc DEVICE (in HBM) or PINNED_HOST (pinned
  * host memory, streamed to the device along the Gram's contraction through a
  * double-buffered copy pipeline: row batches for m >= n, pitched column
- * batches for m < n; FP32 only; the implicit method streams row batches and
- * takes m >= n only).  U: DEVICE FP64 m x k
+ * batches for m < n; FP32 only).  U: DEVICE FP64 m x k
  * column-major (ldu); S: DEVICE FP64 k; V: DEVICE FP64 n x k column-major
  * (ldv).  Triplets past info->k_done are zero.  Synchronises `stream`.
  * Returns OK, NOT_CONVERGED (outputs filled), NONFINITE, INVALID_ARG,

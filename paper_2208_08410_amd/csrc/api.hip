@@ -517,8 +517,9 @@ namespace {
 // Dense t-SVD without the Gram: Algorithm 2's product applied as
 // A^T (A x) (or A (A^T x)) every iteration (Equation 2 evaluated right to
 // left).  A in HBM (any dtype, both branches) or FP32 A in pinned host memory
-// (right branch; streamed once per iteration).  The iterated factor may sit
-// in pinned host memory (A in HBM only).
+// (streamed once per iteration: row batches for the right branch, pitched
+// column batches for the left).  The iterated factor may sit in pinned host
+// memory (A in HBM only).
 tsvd_status dense_implicit(tsvd_ctx* ctx, const void* A, int32_t dtype, int32_t loc, int64_t m, int64_t n, int64_t lda,
                            const tsvd_opts* o, int k, double* U, int64_t ldu, double* S, double* V, int64_t ldv,
                            tsvd_info* info, hipStream_t s) {
@@ -527,7 +528,6 @@ tsvd_status dense_implicit(tsvd_ctx* ctx, const void* A, int32_t dtype, int32_t 
   const int64_t d = right ? n : m, e = right ? m : n;
   const bool pinned = loc == TSVD_LOC_PINNED_HOST;
   const bool host_x = o->factor_loc == TSVD_LOC_PINNED_HOST;
-  if (pinned && !right) return fail(ctx, TSVD_ERR_UNSUPPORTED, "pinned-host A needs the A^T A branch (m >= n)");
   if (pinned && dtype != TSVD_F32) return fail(ctx, TSVD_ERR_UNSUPPORTED, "pinned-host A is FP32");
   if (pinned && host_x) return fail(ctx, TSVD_ERR_UNSUPPORTED, "with A streamed from the host the factor stays on the device");
   const int Q = o->queue_depth > 0 ? o->queue_depth : 2;
@@ -552,19 +552,20 @@ tsvd_status dense_implicit(tsvd_ctx* ctx, const void* A, int32_t dtype, int32_t 
       return fail(ctx, TSVD_ERR_INVALID_ARG, "A is not pinned host memory (allocate it with hipHostMalloc / pin_memory)");
     }
   }
-  // batch rows of a pinned A: rows_per_block rounded up to 128, or 4 GiB of rows
+  // batch rows (right) or columns (left) of a pinned A: rows_per_block rounded
+  // up to 128, or 4 GiB worth rounded down to 128
   int64_t R = 0;
   if (pinned) {
-    R = o->rows_per_block > 0 ? ((o->rows_per_block + 127) / 128) * 128 : (((int64_t)4 << 30) / (n * 4)) / 128 * 128;
+    R = o->rows_per_block > 0 ? ((o->rows_per_block + 127) / 128) * 128 : (((int64_t)4 << 30) / (d * 4)) / 128 * 128;
     if (R < 128) R = 128;
-    if (R > m) R = m;
+    if (R > e) R = e;
   }
-  const int64_t nbatch = pinned ? (m + R - 1) / R : 0;
+  const int64_t nbatch = pinned ? (e + R - 1) / R : 0;
   const int Qa = pinned ? (int)std::min<int64_t>(Q, nbatch) : 0;
-  const size_t buf_bytes = pinned ? align256((size_t)R * n * 4) : 0;
+  const size_t buf_bytes = pinned ? align256((size_t)R * d * 4) : 0;
   const size_t op_bytes =
-      align256((size_t)(pinned ? PinnedDenseOp::ws_doubles(m, n, R) : DenseOp::ws_doubles(m, n)) * 8);
-  const int64_t tiles_total = pinned ? (m + 127) / 128 + nbatch : finish_tiles(m, n, side);
+      align256((size_t)(pinned ? PinnedDenseOp::ws_doubles(m, n, R, right) : DenseOp::ws_doubles(m, n)) * 8);
+  const int64_t tiles_total = pinned ? (e + 127) / 128 + nbatch : finish_tiles(m, n, side);
   const size_t fin_bytes = align256((size_t)(tiles_total + 2) * k * 8);
   const int64_t RX = host_x ? HostFactor::round_rows(d, o->factor_batches > 0 ? o->factor_batches : 1) : 0;
   const int Qx = host_x ? (int)std::min<int64_t>(Q, (d + RX - 1) / RX) : 0;
@@ -586,7 +587,7 @@ tsvd_status dense_implicit(tsvd_ctx* ctx, const void* A, int32_t dtype, int32_t 
   DenseOp dop;
   PinnedDenseOp pop;
   if (pinned) {
-    if (pop.init((const float*)A, m, n, lda, R, Qa, bufs, opws, ctx->copy_stream))
+    if (pop.init((const float*)A, m, n, lda, R, Qa, bufs, opws, ctx->copy_stream, right))
       return fail(ctx, TSVD_ERR_HIP, "batch pipeline events");
   } else {
     dop.setup(A, is_f64, m, n, lda, right, opws);
@@ -618,9 +619,9 @@ tsvd_status dense_implicit(tsvd_ctx* ctx, const void* A, int32_t dtype, int32_t 
       rc = finish_host_factor(op, X, ldx, d, W, ldw, e, S, kd, right, tmp, lw.partial, s);
     } else if (pinned) {
       int64_t tiles = 0;
-      rc = pop.finish(V, ldv, kd, U, ldu, ssq, &tiles, s);
+      rc = pop.finish(X, ldx, kd, W, ldw, ssq, &tiles, s);
       if (!rc) rc = finish_sigma_launch(ssq, tiles, kd, S, s);
-      if (!rc) rc = finish_scale_sign_launch(U, ldu, m, S, V, ldv, n, U, ldu, m, kd, 1, ssq + tiles_total * k, s);
+      if (!rc) rc = finish_scale_sign_launch(W, ldw, e, S, V, ldv, n, U, ldu, m, kd, 1, ssq + tiles_total * k, s);
     } else {
       rc = finish_launch(is_f64, side, A, m, n, lda, X, ldx, kd, W, ldw, S, ssq, s);
       if (!rc)

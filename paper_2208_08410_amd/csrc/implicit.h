@@ -123,9 +123,14 @@ struct DenseOp : ImplicitOp {
 // the copy stream while the previous batch computes t_b = A_b x and its share
 // of A_b^T t_b), so the host link bounds it (the paper's degree-1 dense case,
 // the time/memory trade-off of Sec. IV's implicit product)
+// A in pinned host memory, streamed once per product through Q device
+// buffers: row batches A_b for the right branch (z = sum_b A_b^T (A_b x)),
+// pitched column batches A_c for the left branch (z = sum_c A_c (A_c^T x)),
+// the batches' contributions added in batch order.
 struct PinnedDenseOp : ImplicitOp {
   const float* A = nullptr;
   int64_t m = 0, n = 0, lda = 0, R = 0, nbatch = 0;
+  bool right = true;       // row batches (A^T A branch) or column batches (A A^T branch)
   int Q = 0;
   float* buf[16];
   hipStream_t cs = nullptr;
@@ -135,17 +140,20 @@ struct PinnedDenseOp : ImplicitOp {
   int made = 0;
   int64_t slab_rows = 0, slabs = 0;
   double* part = nullptr;
-  double* t = nullptr;  // m
+  double* t = nullptr;      // right: m (A x); left: R (one batch's A_c^T x)
+  double* zpart = nullptr;  // left: nbatch x m (each batch's A_c t_c)
   int64_t h2d = 0;
   ~PinnedDenseOp() override;
-  static int64_t ws_doubles(int64_t m, int64_t n, int64_t R);
+  // R: rows (right) or columns (left) per batch
+  static int64_t ws_doubles(int64_t m, int64_t n, int64_t R, bool right);
   int init(const float* A, int64_t m, int64_t n, int64_t lda, int64_t R, int Q, float* const* bufs, double* ws,
-           hipStream_t cs);
+           hipStream_t cs, bool right);
   int apply(const double* x, const float* xf, double* z, hipStream_t s) override;
   // Algorithm 1's finishing product for all kd columns at once, one more pass
-  // over A: U = A V (FP64) with column sums of squares per 128-row tile in ssq;
-  // *tiles = the tile count
-  int finish(const double* V, int64_t ldv, int kd, double* U, int64_t ldu, double* ssq, int64_t* tiles, hipStream_t s);
+  // over A: W = A X (right: U = A V) or W = A^T X (left: V = A^T U), FP64,
+  // with column sums of squares per 128-row tile of W in ssq; *tiles = the
+  // tile count
+  int finish(const double* X, int64_t ldx, int kd, double* W, int64_t ldw, double* ssq, int64_t* tiles, hipStream_t s);
   int64_t h2d_bytes() const override { return h2d; }
 };
 

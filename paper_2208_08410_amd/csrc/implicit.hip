@@ -497,7 +497,12 @@ int DenseOp::first(const double* x, double* w, hipStream_t s) {
   return reduce_slabs_launch(part, slabs, n, w, nullptr, s);
 }
 
-int64_t PinnedDenseOp::ws_doubles(int64_t m, int64_t n, int64_t R) {
+int64_t PinnedDenseOp::ws_doubles(int64_t m, int64_t n, int64_t R, bool right) {
+  if (!right) {
+    const int64_t nb = (n + R - 1) / R;
+    const int64_t sl = gemv_cols_slabs(m, gemv_cols_slab_rows(m, R));
+    return sl * R + R + nb * m + 64;
+  }
   const int64_t nb = (m + R - 1) / R;
   const int64_t sr = gemv_cols_slab_rows(R, n);
   int64_t slabs = 0;
@@ -506,21 +511,31 @@ int64_t PinnedDenseOp::ws_doubles(int64_t m, int64_t n, int64_t R) {
 }
 
 int PinnedDenseOp::init(const float* A_, int64_t m_, int64_t n_, int64_t lda_, int64_t R_, int Q_, float* const* bufs,
-                        double* ws, hipStream_t cs_) {
+                        double* ws, hipStream_t cs_, bool right_) {
   A = A_;
   m = m_;
   n = n_;
   lda = lda_;
   R = R_;
-  nbatch = (m + R - 1) / R;
+  right = right_;
+  nbatch = right ? (m + R - 1) / R : (n + R - 1) / R;
   Q = Q_;
   cs = cs_;
   for (int q = 0; q < Q; q++) buf[q] = bufs[q];
-  slab_rows = gemv_cols_slab_rows(R, n);
-  slabs = 0;
-  for (int64_t b = 0; b < nbatch; b++) slabs += gemv_cols_slabs(std::min(R, m - b * R), slab_rows);
-  part = ws;
-  t = part + slabs * n;
+  if (right) {
+    slab_rows = gemv_cols_slab_rows(R, n);
+    slabs = 0;
+    for (int64_t b = 0; b < nbatch; b++) slabs += gemv_cols_slabs(std::min(R, m - b * R), slab_rows);
+    part = ws;
+    t = part + slabs * n;
+  } else {
+    // one batch's A_c^T x in slabs of the m rows, then A_c t_c per batch
+    slab_rows = gemv_cols_slab_rows(m, R);
+    slabs = gemv_cols_slabs(m, slab_rows);
+    part = ws;
+    t = part + slabs * R;
+    zpart = t + R;
+  }
   if (hipEventCreateWithFlags(&start_ev, hipEventDisableTiming) != hipSuccess) return TSVD_ERR_HIP;
   have_start = true;
   for (; made < Q; made++) {
@@ -544,49 +559,65 @@ PinnedDenseOp::~PinnedDenseOp() {
 }
 
 // one pass over A per product: batch b is copied into slot b % Q while the
-// previous batch computes t_b = A_b x and its slabs of A_b^T t_b
+// previous batch computes its contribution (right: t_b = A_b x and its slabs
+// of A_b^T t_b; left: t_c = A_c^T x, then A_c t_c)
 int PinnedDenseOp::apply(const double* x, const float* xf, double* z, hipStream_t s) {
-  (void)x;
   TSVD_HIP_TRY(hipEventRecord(start_ev, s));  // x is ready: the copies may start
   TSVD_HIP_TRY(hipStreamWaitEvent(cs, start_ev, 0));
   int64_t slab0 = 0;
   for (int64_t b = 0; b < nbatch; b++) {
     const int q = (int)(b % Q);
-    const int64_t r0 = b * R, rows = std::min(R, m - r0);
+    const int64_t r0 = b * R, len = std::min(R, (right ? m : n) - r0);
     if (used[q]) TSVD_HIP_TRY(hipStreamWaitEvent(cs, consumed[q], 0));
-    TSVD_HIP_TRY(hipMemcpy2DAsync(buf[q], (size_t)n * 4, A + r0 * lda, (size_t)lda * 4, (size_t)n * 4, (size_t)rows,
-                                  hipMemcpyHostToDevice, cs));
+    if (right)
+      TSVD_HIP_TRY(hipMemcpy2DAsync(buf[q], (size_t)n * 4, A + r0 * lda, (size_t)lda * 4, (size_t)n * 4, (size_t)len,
+                                    hipMemcpyHostToDevice, cs));
+    else
+      TSVD_HIP_TRY(hipMemcpy2DAsync(buf[q], (size_t)len * 4, A + r0, (size_t)lda * 4, (size_t)len * 4, (size_t)m,
+                                    hipMemcpyHostToDevice, cs));
     TSVD_HIP_TRY(hipEventRecord(copied[q], cs));
     TSVD_HIP_TRY(hipStreamWaitEvent(s, copied[q], 0));
-    if (int rc = gemv_rows_launch(0, buf[q], rows, n, n, xf, 0, t + r0, nullptr, s)) return rc;
-    if (int rc = gemv_cols_partial_launch(0, buf[q], rows, n, n, t + r0, slab_rows, part + slab0 * n, s)) return rc;
+    if (right) {
+      if (int rc = gemv_rows_launch(0, buf[q], len, n, n, xf, 0, t + r0, nullptr, s)) return rc;
+      if (int rc = gemv_cols_partial_launch(0, buf[q], len, n, n, t + r0, slab_rows, part + slab0 * n, s)) return rc;
+      slab0 += gemv_cols_slabs(len, slab_rows);
+    } else {
+      if (int rc = gemv_cols_partial_launch(0, buf[q], m, len, len, x, slab_rows, part, s)) return rc;
+      if (int rc = reduce_slabs_launch(part, slabs, len, t, nullptr, s)) return rc;
+      if (int rc = gemv_rows_launch(0, buf[q], m, len, len, t, 1, zpart + b * m, nullptr, s)) return rc;
+    }
     TSVD_HIP_TRY(hipEventRecord(consumed[q], s));
     used[q] = true;
-    slab0 += gemv_cols_slabs(rows, slab_rows);
-    h2d += rows * n * 4;
+    h2d += len * (right ? n : m) * 4;
   }
-  return reduce_slabs_launch(part, slabs, n, z, nullptr, s);
+  return right ? reduce_slabs_launch(part, slabs, n, z, nullptr, s) : reduce_slabs_launch(zpart, nbatch, m, z, nullptr, s);
 }
 
-int PinnedDenseOp::finish(const double* V, int64_t ldv, int kd, double* U, int64_t ldu, double* ssq, int64_t* tiles,
+int PinnedDenseOp::finish(const double* X, int64_t ldx, int kd, double* W, int64_t ldw, double* ssq, int64_t* tiles,
                           hipStream_t s) {
   TSVD_HIP_TRY(hipEventRecord(start_ev, s));
   TSVD_HIP_TRY(hipStreamWaitEvent(cs, start_ev, 0));
   int64_t tile_off = 0;
   for (int64_t b = 0; b < nbatch; b++) {
     const int q = (int)(b % Q);
-    const int64_t r0 = b * R, rows = std::min(R, m - r0);
+    const int64_t r0 = b * R, len = std::min(R, (right ? m : n) - r0);
     if (used[q]) TSVD_HIP_TRY(hipStreamWaitEvent(cs, consumed[q], 0));
-    TSVD_HIP_TRY(hipMemcpy2DAsync(buf[q], (size_t)n * 4, A + r0 * lda, (size_t)lda * 4, (size_t)n * 4, (size_t)rows,
-                                  hipMemcpyHostToDevice, cs));
+    if (right)
+      TSVD_HIP_TRY(hipMemcpy2DAsync(buf[q], (size_t)n * 4, A + r0 * lda, (size_t)lda * 4, (size_t)n * 4, (size_t)len,
+                                    hipMemcpyHostToDevice, cs));
+    else
+      TSVD_HIP_TRY(hipMemcpy2DAsync(buf[q], (size_t)len * 4, A + r0, (size_t)lda * 4, (size_t)len * 4, (size_t)m,
+                                    hipMemcpyHostToDevice, cs));
     TSVD_HIP_TRY(hipEventRecord(copied[q], cs));
     TSVD_HIP_TRY(hipStreamWaitEvent(s, copied[q], 0));
-    if (int rc = finish_gemm_launch(0, 0, buf[q], rows, n, n, V, ldv, kd, U + r0, ldu, ssq + tile_off * kd, s))
-      return rc;
+    // the batch's rows of W: rows r0.. of U = A V, or of V = A^T U
+    const int rc = right ? finish_gemm_launch(0, 0, buf[q], len, n, n, X, ldx, kd, W + r0, ldw, ssq + tile_off * kd, s)
+                         : finish_gemm_launch(0, 1, buf[q], m, len, len, X, ldx, kd, W + r0, ldw, ssq + tile_off * kd, s);
+    if (rc) return rc;
     TSVD_HIP_TRY(hipEventRecord(consumed[q], s));
     used[q] = true;
-    tile_off += (rows + 127) / 128;
-    h2d += rows * n * 4;
+    tile_off += (len + 127) / 128;
+    h2d += len * (right ? n : m) * 4;
   }
   *tiles = tile_off;
   return 0;

@@ -90,6 +90,29 @@ def test_pinned_implicit_vs_oracle(ctx, qd, rows):
     assert np.allclose(S.cpu().numpy(), Sd.cpu().numpy(), rtol=1e-12)
 
 
+@pytest.mark.parametrize("qd,cols", [(1, 700), (2, 700), (3, 1000)])
+def test_pinned_implicit_left_branch_vs_oracle(ctx, qd, cols):
+    """m < n with A in pinned host memory: streamed once per iteration in
+    pitched column batches (ragged last batch), z = sum_c A_c (A_c^T u),
+    against the oracle's left branch (Eq. 3); the same run on the
+    device-resident A agrees to rounding."""
+    import torch
+    m, n, k = 600, 4500, 4
+    dk = synth.dense_known(m, n, synth.spectrum_geometric(0.9, m), seed=33, dtype=np.float32)
+    st = synth.start_vectors(k, m, seed=34)
+    A64 = dk.A.astype(np.float64)
+    ref = O.tsvd_implicit(lambda x: A64 @ x, lambda y: A64.T @ y, (m, n), 1e-10, k, st)
+    Ah = torch.from_numpy(dk.A).pin_memory()
+    U, S, V, info = P.tsvd_dense(ctx, Ah, k, 1e-10, to_dev(st), fixed_iters=ref.iters, method="implicit",
+                                 rows_per_block=cols, queue_depth=qd)
+    assert not info["branch_right"]
+    it = int(np.sum(ref.iters))
+    assert info["h2d_bytes"] == m * n * 4 * (it + 1)
+    compare(ref, U, S, V, k, 1e-8, 1e-5)
+    Ud, Sd, Vd, _ = P.tsvd_dense(ctx, to_dev(dk.A), k, 1e-10, to_dev(st), fixed_iters=ref.iters, method="implicit")
+    assert np.allclose(S.cpu().numpy(), Sd.cpu().numpy(), rtol=1e-12)
+
+
 @pytest.mark.parametrize("dt", [np.float64, np.float32])
 def test_gram_loop_power_vs_oracle(ctx, dt):
     """tsvd_power_gram on the host-driven loop (B streamed from HBM per

@@ -55,16 +55,16 @@ def test_pinned_batches_vs_oracle(ctx, rpb, q):
         assert line_angle(U[:, l], Ur[:, l]) < 1e-4
 
 
-def test_pinned_rejects_pageable_and_implicit_left_branch(ctx):
+def test_pinned_rejects_pageable_and_host_factor(ctx):
     import torch
     A = torch.from_numpy(synth.gaussian_dense(100, 50, seed=1))
     st = to_dev(synth.start_vectors(2, 50, seed=1))
     with pytest.raises(ValueError):
         P.tsvd_dense(ctx, A, 2, 1e-8, st)  # pageable memory is refused by the binding
-    # the implicit product streams row batches only (the A^T A branch)
-    Aw = pinned(synth.gaussian_dense(50, 100, seed=1))
+    # with A streamed from the host, the iterated factor stays on the device
+    Ap = pinned(synth.gaussian_dense(100, 50, seed=1))
     with pytest.raises(P.TsvdError) as e:
-        P.tsvd_dense(ctx, Aw, 2, 1e-8, to_dev(synth.start_vectors(2, 50, seed=1)), method="implicit")
+        P.tsvd_dense(ctx, Ap, 2, 1e-8, st, method="implicit", factor="host")
     assert e.value.status == P.UNSUPPORTED
 
 
