@@ -108,6 +108,8 @@ struct DenseOp : ImplicitOp {
   int a_f64 = 0;
   int64_t m = 0, n = 0, lda = 0;
   bool right = true;
+  // right: slabs of every row batch, side by side (n wide); left: slabs of
+  // the m rows of one column batch (R wide), reused batch after batch
   int64_t slab_rows = 0, slabs = 0;
   double* part = nullptr;  // slabs x n
   double* t = nullptr;     // max(m, n)
@@ -138,6 +140,8 @@ struct PinnedDenseOp : ImplicitOp {
   bool used[16];
   bool have_start = false;
   int made = 0;
+  // right: slabs of every row batch, side by side (n wide); left: slabs of
+  // the m rows of one column batch (R wide), reused batch after batch
   int64_t slab_rows = 0, slabs = 0;
   double* part = nullptr;
   double* t = nullptr;      // right: m (A x); left: R (one batch's A_c^T x)
