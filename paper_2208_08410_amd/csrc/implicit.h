@@ -159,6 +159,7 @@ struct PinnedDenseOp : ImplicitOp {
   // tile count
   int finish(const double* X, int64_t ldx, int kd, double* W, int64_t ldw, double* ssq, int64_t* tiles, hipStream_t s);
   int64_t h2d_bytes() const override { return h2d; }
+  int copy_batch(int64_t r0, int64_t len, int q, hipStream_t s);
 };
 
 // device workspace of implicit_power

@@ -558,6 +558,21 @@ PinnedDenseOp::~PinnedDenseOp() {
   if (have_start) (void)hipEventDestroy(start_ev);
 }
 
+// batch [r0, r0 + len) of rows (right) or columns (left) into slot q on the
+// copy stream, once the slot's previous batch is consumed; `s` waits for it
+int PinnedDenseOp::copy_batch(int64_t r0, int64_t len, int q, hipStream_t s) {
+  if (used[q]) TSVD_HIP_TRY(hipStreamWaitEvent(cs, consumed[q], 0));
+  if (right)
+    TSVD_HIP_TRY(hipMemcpy2DAsync(buf[q], (size_t)n * 4, A + r0 * lda, (size_t)lda * 4, (size_t)n * 4, (size_t)len,
+                                  hipMemcpyHostToDevice, cs));
+  else
+    TSVD_HIP_TRY(hipMemcpy2DAsync(buf[q], (size_t)len * 4, A + r0, (size_t)lda * 4, (size_t)len * 4, (size_t)m,
+                                  hipMemcpyHostToDevice, cs));
+  TSVD_HIP_TRY(hipEventRecord(copied[q], cs));
+  TSVD_HIP_TRY(hipStreamWaitEvent(s, copied[q], 0));
+  return 0;
+}
+
 // one pass over A per product: batch b is copied into slot b % Q while the
 // previous batch computes its contribution (right: t_b = A_b x and its slabs
 // of A_b^T t_b; left: t_c = A_c^T x, then A_c t_c)
@@ -568,15 +583,7 @@ int PinnedDenseOp::apply(const double* x, const float* xf, double* z, hipStream_
   for (int64_t b = 0; b < nbatch; b++) {
     const int q = (int)(b % Q);
     const int64_t r0 = b * R, len = std::min(R, (right ? m : n) - r0);
-    if (used[q]) TSVD_HIP_TRY(hipStreamWaitEvent(cs, consumed[q], 0));
-    if (right)
-      TSVD_HIP_TRY(hipMemcpy2DAsync(buf[q], (size_t)n * 4, A + r0 * lda, (size_t)lda * 4, (size_t)n * 4, (size_t)len,
-                                    hipMemcpyHostToDevice, cs));
-    else
-      TSVD_HIP_TRY(hipMemcpy2DAsync(buf[q], (size_t)len * 4, A + r0, (size_t)lda * 4, (size_t)len * 4, (size_t)m,
-                                    hipMemcpyHostToDevice, cs));
-    TSVD_HIP_TRY(hipEventRecord(copied[q], cs));
-    TSVD_HIP_TRY(hipStreamWaitEvent(s, copied[q], 0));
+    if (int rc = copy_batch(r0, len, q, s)) return rc;
     if (right) {
       if (int rc = gemv_rows_launch(0, buf[q], len, n, n, xf, 0, t + r0, nullptr, s)) return rc;
       if (int rc = gemv_cols_partial_launch(0, buf[q], len, n, n, t + r0, slab_rows, part + slab0 * n, s)) return rc;
@@ -601,15 +608,7 @@ int PinnedDenseOp::finish(const double* X, int64_t ldx, int kd, double* W, int64
   for (int64_t b = 0; b < nbatch; b++) {
     const int q = (int)(b % Q);
     const int64_t r0 = b * R, len = std::min(R, (right ? m : n) - r0);
-    if (used[q]) TSVD_HIP_TRY(hipStreamWaitEvent(cs, consumed[q], 0));
-    if (right)
-      TSVD_HIP_TRY(hipMemcpy2DAsync(buf[q], (size_t)n * 4, A + r0 * lda, (size_t)lda * 4, (size_t)n * 4, (size_t)len,
-                                    hipMemcpyHostToDevice, cs));
-    else
-      TSVD_HIP_TRY(hipMemcpy2DAsync(buf[q], (size_t)len * 4, A + r0, (size_t)lda * 4, (size_t)len * 4, (size_t)m,
-                                    hipMemcpyHostToDevice, cs));
-    TSVD_HIP_TRY(hipEventRecord(copied[q], cs));
-    TSVD_HIP_TRY(hipStreamWaitEvent(s, copied[q], 0));
+    if (int rc = copy_batch(r0, len, q, s)) return rc;
     // the batch's rows of W: rows r0.. of U = A V, or of V = A^T U
     const int rc = right ? finish_gemm_launch(0, 0, buf[q], len, n, n, X, ldx, kd, W + r0, ldw, ssq + tile_off * kd, s)
                          : finish_gemm_launch(0, 1, buf[q], m, len, len, X, ldx, kd, W + r0, ldw, ssq + tile_off * kd, s);
