@@ -276,7 +276,8 @@ typedef struct {
 /* Algorithm 1 for `count` independent problems of any mix of shapes.  One
  * persistent engine launch takes work items from one list in order: per
  * problem (queued longest first) its Gram units (problem x split-K chunk x
- * triangle tile, Algorithm 3's block products), the reduction of each tile's
+ * triangle tile, Algorithm 3's block products; tile edge and chunk rows per
+ * Gram-dimension class from the context's tuning), the reduction of each tile's
  * chunk partials into the problem's B, and the seats of its power team (a
  * team runs Algorithm 2 with deflation on its problem, then its members take
  * further items), so later problems' Gram work runs beside earlier problems'
