@@ -51,3 +51,24 @@ def test_cache_round_trip(tmp_path):
     assert data["dense/bf16x3/R/d4096/K262144"]["tuning"]["gram_tile"] == 256
     t2 = T.Tuner(FakeCtx(), path)
     assert t2.lookup("dense/bf16x3/R/d4096/K262144") == {"gram_tile": 256, "gram_chunks": 0, "power_blocks": 0}
+
+
+def test_gram_unit_candidates_and_class_table(tmp_path):
+    """Per-class batched Gram units: both tile edges, chunk lengths up to
+    twice the class's longest contraction; the stored classes come back as
+    the group_tile / group_kchunk_cls tuning arrays (0 for untuned classes)."""
+    import paper_2208_08410_amd as P
+    c = T.gram_unit_candidates(300)
+    assert c == [(64, 512), (128, 512)]
+    c = T.gram_unit_candidates(65536)
+    assert {t for t, _ in c} == {64, 128} and max(kc for _, kc in c) == 8192
+    assert T.gram_unit_key(3) == "gram_unit/c3"
+    t = T.Tuner(FakeCtx(), str(tmp_path / "t.json"))
+    empty = t.class_tuning()
+    assert empty == {"group_tile": [0] * P.GRAM_CLASSES, "group_kchunk_cls": [0] * P.GRAM_CLASSES}
+    t._record(T.gram_unit_key(1), {"group_tile": 64, "group_kchunk": 1024}, 1.0, [])
+    t._record(T.gram_unit_key(5), {"group_tile": 128, "group_kchunk": 4096}, 1.0, [])
+    ct = t.class_tuning()
+    assert ct["group_tile"][1] == 64 and ct["group_kchunk_cls"][1] == 1024
+    assert ct["group_tile"][5] == 128 and ct["group_kchunk_cls"][5] == 4096
+    assert sum(1 for v in ct["group_tile"] if v) == 2
